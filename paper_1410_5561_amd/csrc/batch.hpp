@@ -1,0 +1,16 @@
+// Batched form: many grids in one persistent, graph-captured launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/mwd_stencil.h"
+
+namespace mwd {
+
+struct BatchState;
+
+int batch_run(int plan_kind, int plan_dtype, BatchState** state, stencil_grid* grids,
+              const stencil_coeffs* coeffs, int n, int T, hipStream_t stream);
+void batch_free(BatchState* s);
+
+}  // namespace mwd

@@ -1,0 +1,62 @@
+// Host-side internal interfaces between the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace mwd {
+
+enum Kind : int { K7C = 0, K7V = 1, K25C = 2, K25V = 3 };
+
+inline int radius_of(int kind) { return (kind == K7C || kind == K7V) ? 1 : 4; }
+inline int narr_of(int kind) { return kind == K7V ? 7 : (kind == K25V ? 13 : 0); }
+inline int ndomain_of(int kind) { return kind == K7C ? 2 : kind == K7V ? 9 : kind == K25C ? 2 : 15; }
+
+// A grid as the kernels see it: pointers to the interior origin (element
+// (0,0,0)) of each buffer; halo >= R cells exist on every side.
+struct DevGrid {
+    int nx, ny, nz, halo;
+    long long sy, sz;
+    int dtype;   // 0 = f64, 1 = f32
+    int cur;     // buffer holding the current level
+    void* org[2];
+};
+
+// Host copy of the weights: constants in double, arrays as interior-origin
+// device pointers.
+struct HostWeights {
+    int kind;
+    double c[13];
+    const void* org[13];
+};
+
+// One full sweep: dst <- op(src) over the interior.
+hipError_t naive_sweep(const DevGrid& g, const HostWeights& w, const void* src, void* dst,
+                       hipStream_t stream);
+
+// MWD schedule parameters resolved for one (kind, dtype).
+struct MwdShape {
+    int dw;      // diamond width
+    int wpr;     // waves per diamond row (lanes = 64 * wpr)
+    int lanes() const { return 64 * wpr; }
+};
+
+// True if a compiled MWD kernel exists for (kind, dtype, shape).
+bool mwd_supported(int kind, int dtype, const MwdShape& s);
+int mwd_levels(int kind, const MwdShape& s);
+int mwd_xtile(int kind, const MwdShape& s);
+
+// Run T steps with MWD.  `scratch` holds two extra grid-sized buffer pairs
+// (4 pointers at the interior origin, same strides as g).
+hipError_t mwd_run(const DevGrid& g, const HostWeights& w, int T, const MwdShape& s,
+                   void* const scratch[4], hipStream_t stream);
+
+// FP64 norms: which 0 -> of a, which 1 -> of a - b (b may be another dtype).
+hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b,
+                      int which, double out[2], hipStream_t stream);
+
+void set_last_error(const std::string& s);
+
+}  // namespace mwd

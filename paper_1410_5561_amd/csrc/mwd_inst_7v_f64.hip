@@ -1,0 +1,17 @@
+// MWD instantiations for the 7v stencil in f64.
+#include "mwd_rows.hpp"
+
+namespace mwd {
+
+static const MwdEntry kEntries[] = {
+    MWD_ENTRY(K7V, double, 0, 4, 1), MWD_ENTRY(K7V, double, 0, 4, 2), MWD_ENTRY(K7V, double, 0, 8, 1),
+    MWD_ENTRY(K7V, double, 0, 8, 2),
+};
+
+void mwd_table_7v_f64(const MwdEntry** tab, int* n)
+{
+    *tab = kEntries;
+    *n = (int)(sizeof(kEntries) / sizeof(kEntries[0]));
+}
+
+}  // namespace mwd

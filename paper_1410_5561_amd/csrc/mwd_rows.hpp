@@ -1,0 +1,101 @@
+// MWD row kernel, final gather and the per-instantiation row scheduler.
+// Included by the mwd_inst_*.hip files, one per (kind, dtype), so that the
+// kernel instantiations compile in parallel.
+#pragma once
+
+#include "internal.hpp"
+#include "mwd_tile.hpp"
+
+namespace mwd {
+
+template <int K, typename T, int DW, int WPR>
+__global__ void __launch_bounds__(64 * DW * WPR)
+mwd_row_kernel(MwdArgs<T> a)
+{
+    using G = MwdGeom<K, DW, WPR>;
+    __shared__ T ex[2][G::L][G::NS][G::LX];
+    const int b = blockIdx.x / a.nxt;
+    const int j = blockIdx.x % a.nxt;
+    mwd_tile<K, T, DW, WPR>(a, b, j, ex);
+}
+
+// After the last row, copy u_T and u_{T-1} of every point out of the pair
+// that holds them into the caller's buffers (pair 0).
+template <typename T, int R, int DW>
+__global__ void __launch_bounds__(256)
+mwd_gather_kernel(MwdArgs<T> a)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const long long off = (long long)z * a.sz + (long long)y * a.sy + x;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int t = a.nsteps - k;
+        if (t < 1) continue;
+        const int p = pair_of_row(row_of<R, DW>(y, t));
+        if (p != 0) {
+            const int bi = (a.cur + t) & 1;
+            a.pair[0][bi][off] = a.pair[p][bi][off];
+        }
+    }
+}
+
+template <int K, typename T, int DW, int WPR>
+static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, void* const scratch[4],
+                           hipStream_t stream)
+{
+    using G = MwdGeom<K, DW, WPR>;
+    MwdArgs<T> a{};
+    T* o0 = static_cast<T*>(g.org[0]);
+    T* o1 = static_cast<T*>(g.org[1]);
+    a.pair[0][0] = o0;
+    a.pair[0][1] = o1;
+    a.pair[1][0] = static_cast<T*>(scratch[0]);
+    a.pair[1][1] = static_cast<T*>(scratch[1]);
+    a.pair[2][0] = static_cast<T*>(scratch[2]);
+    a.pair[2][1] = static_cast<T*>(scratch[3]);
+    a.halo = static_cast<const T*>(g.org[g.cur]);
+    for (int m = 0; m < 13; ++m) {
+        a.w.c[m] = static_cast<T>(hw.c[m]);
+        a.w.arr[m] = static_cast<const T*>(hw.org[m]);
+    }
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.sy = g.sy;
+    a.sz = g.sz;
+    a.cur = g.cur;
+    a.nsteps = nsteps;
+    a.nxt = (g.nx + G::XT - 1) / G::XT;
+    const int rho_max = (nsteps + G::H - 1) / G::H;
+    for (int rho = 0; rho <= rho_max; ++rho) {
+        a.rho = rho;
+        a.t0 = (rho - 1) * G::H;
+        const int yoff = (rho % 2) * (DW / 2);
+        a.ybase = yoff > 0 ? yoff - DW : 0;
+        const int nB = (g.ny - 1 - a.ybase) / DW + 1;
+        hipLaunchKernelGGL((mwd_row_kernel<K, T, DW, WPR>), dim3(nB * a.nxt), dim3(G::NT), 0, stream, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    dim3 gg((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    hipLaunchKernelGGL((mwd_gather_kernel<T, G::R, DW>), gg, dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+using RunFn = hipError_t (*)(const DevGrid&, const HostWeights&, int, void* const*, hipStream_t);
+
+struct MwdEntry {
+    int kind, dtype, dw, wpr;
+    RunFn fn;
+    int levels, xtile;
+};
+
+#define MWD_ENTRY(K, TT, DTI, DW, WPR)                                               \
+    MwdEntry{K, DTI, DW, WPR, &run_rows<K, TT, DW, WPR>, MwdGeom<K, DW, WPR>::L,     \
+             MwdGeom<K, DW, WPR>::XT}
+
+
+}  // namespace mwd

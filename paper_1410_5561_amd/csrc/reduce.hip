@@ -1,0 +1,137 @@
+// FP64 norms over the interior of a grid (or of a difference of two grids),
+// accumulated in FP64 whatever the storage precision: two passes, per-block
+// partial sums and maxima, then one block combines them in a fixed order, so
+// a result is reproducible run to run.
+#include <mutex>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mwd {
+
+constexpr int kNormThreads = 256;
+constexpr int kNormMaxBlocks = 2048;
+
+template <typename TA, typename TB, bool DIFF>
+__global__ void __launch_bounds__(kNormThreads)
+norm_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, int nx, int ny, int nz,
+                    long long asy, long long asz, long long bsy, long long bsz,
+                    double* __restrict__ part)
+{
+    __shared__ double ssum[kNormThreads];
+    __shared__ double smax[kNormThreads];
+    double s = 0.0, m = 0.0;
+    const long long rows = (long long)ny * nz;
+    // one (y, z) row per block iteration; lanes stride along x
+    for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % ny), z = (int)(r / ny);
+        const TA* ar = a + z * asz + (long long)y * asy;
+        const TB* br = DIFF ? b + z * bsz + (long long)y * bsy : nullptr;
+        for (int x = threadIdx.x; x < nx; x += kNormThreads) {
+            double v = (double)ar[x];
+            if (DIFF) v = v - (double)br[x];
+            s += v * v;
+            m = fmax(m, fabs(v));
+        }
+    }
+    ssum[threadIdx.x] = s;
+    smax[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ssum[0];
+        part[2 * blockIdx.x + 1] = smax[0];
+    }
+}
+
+__global__ void __launch_bounds__(kNormThreads)
+norm_final_kernel(const double* __restrict__ part, int nblocks, double* __restrict__ out)
+{
+    __shared__ double ssum[kNormThreads];
+    __shared__ double smax[kNormThreads];
+    double s = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += kNormThreads) {
+        s += part[2 * i];
+        m = fmax(m, part[2 * i + 1]);
+    }
+    ssum[threadIdx.x] = s;
+    smax[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(ssum[0]);
+        out[1] = smax[0];
+    }
+}
+
+// Device scratch for the partials, one per device, kept for the process.
+static std::mutex g_norm_mu;
+static double* g_norm_buf[64] = {nullptr};
+
+static hipError_t norm_buffer(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_norm_mu);
+    if (!g_norm_buf[dev]) {
+        e = hipMalloc(&g_norm_buf[dev], sizeof(double) * (2 * kNormMaxBlocks + 2));
+        if (e != hipSuccess) return e;
+    }
+    *out = g_norm_buf[dev];
+    return hipSuccess;
+}
+
+template <typename TA, typename TB>
+static void launch_norm(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b, bool diff,
+                        int nblocks, double* part, hipStream_t stream)
+{
+    if (diff)
+        hipLaunchKernelGGL((norm_partial_kernel<TA, TB, true>), dim3(nblocks), dim3(kNormThreads), 0,
+                           stream, static_cast<const TA*>(a), static_cast<const TB*>(b), ga.nx, ga.ny,
+                           ga.nz, ga.sy, ga.sz, gb.sy, gb.sz, part);
+    else
+        hipLaunchKernelGGL((norm_partial_kernel<TA, TB, false>), dim3(nblocks), dim3(kNormThreads), 0,
+                           stream, static_cast<const TA*>(a), static_cast<const TB*>(b), ga.nx, ga.ny,
+                           ga.nz, ga.sy, ga.sz, gb.sy, gb.sz, part);
+}
+
+hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b, int which,
+                      double out[2], hipStream_t stream)
+{
+    double* buf = nullptr;
+    hipError_t e = norm_buffer(&buf);
+    if (e != hipSuccess) return e;
+    const long long rows = (long long)ga.ny * ga.nz;
+    const int nblocks = (int)(rows < kNormMaxBlocks ? rows : kNormMaxBlocks);
+    const bool diff = which != 0;
+    const bool fa = ga.dtype == 0, fb = gb.dtype == 0;
+    if (fa && fb) launch_norm<double, double>(ga, a, gb, b, diff, nblocks, buf, stream);
+    else if (fa && !fb) launch_norm<double, float>(ga, a, gb, b, diff, nblocks, buf, stream);
+    else if (!fa && fb) launch_norm<float, double>(ga, a, gb, b, diff, nblocks, buf, stream);
+    else launch_norm<float, float>(ga, a, gb, b, diff, nblocks, buf, stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormThreads), 0, stream, buf, nblocks,
+                       buf + 2 * kNormMaxBlocks);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(out, buf + 2 * kNormMaxBlocks, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(stream);
+}
+
+}  // namespace mwd

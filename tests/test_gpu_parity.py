@@ -1,0 +1,142 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: bit-exact.  The kernels evaluate each update in the listings' order with
+separately rounded operations, like the oracle, so FP64 and FP32 results are
+identical to the oracle run in the same precision; the FP32 form is also
+held to a stated error bound against the FP64 oracle.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gridgen
+import oracle
+from gpu_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(kind, n, dtype, seed=11):
+    R = gridgen.RADIUS[kind]
+    u0 = gridgen.field(seed, *n, R, -1.0, 1.0, dtype)
+    if kind == "7c":
+        co = gridgen.C7
+    elif kind == "25c":
+        co = gridgen.C25
+    elif kind == "7v":
+        co = [c.astype(dtype) for c in gridgen.coeffs_7v(seed, *n, R)]
+    else:
+        rng = np.random.default_rng(seed)
+        co = [rng.uniform(0, 0.07, size=u0.shape).astype(dtype) for _ in range(13)]
+    return u0, co
+
+
+def _check(kind, u0, co, T, got_T, got_Tm1):
+    uT, uTm1 = oracle.run(kind, u0, co, T)
+    assert np.array_equal(got_T, uT), "u_T differs: max |d| = %g" % np.nanmax(np.abs(got_T - uT))
+    if T > 0:
+        assert np.array_equal(got_Tm1, uTm1), "u_{T-1} differs"
+
+
+KINDS = ["7c", "7v", "25c", "25v"]
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_naive_bitexact(kind, dtype):
+    n = (70, 37, 21)   # two x blocks, ragged y and z
+    print("naive", kind, np.dtype(dtype).name, n, flush=True)
+    u0, co = _inputs(kind, n, dtype)
+    got = run_gpu(kind, u0, co, 5, mode="naive")
+    _check(kind, u0, co, 5, *got)
+
+
+MWD_SHAPES = {
+    ("7c", "f64"): [(4, 64), (4, 128), (8, 64), (8, 128)],
+    ("7c", "f32"): [(4, 64), (4, 128), (8, 64), (8, 128), (16, 64)],
+    ("7v", "f64"): [(4, 64), (4, 128), (8, 64), (8, 128)],
+    ("7v", "f32"): [(4, 64), (4, 128), (8, 64), (8, 128), (16, 64)],
+    ("25c", "f64"): [(8, 64), (16, 64)],
+    ("25c", "f32"): [(8, 64), (16, 64)],
+    ("25v", "f64"): [(8, 64), (16, 64)],
+    ("25v", "f32"): [(8, 64), (16, 64)],
+}
+MWD_CASES = [(k, d, dw, lx) for (k, d), shapes in MWD_SHAPES.items() for (dw, lx) in shapes]
+
+
+@pytest.mark.parametrize("case", MWD_CASES, ids=lambda c: "%s-%s-dw%d-lx%d" % c)
+def test_mwd_bitexact(case):
+    kind, dts, dw, lanes = case
+    dtype = np.float64 if dts == "f64" else np.float32
+    # several x tiles with a ragged last one, several diamonds per row with
+    # half diamonds at both y edges, many rows
+    n = (150, 45, 19) if kind in ("7c", "7v") else (140, 53, 17)
+    T = 13 if kind in ("7c", "7v") else 7
+    print("mwd", case, n, T, flush=True)
+    u0, co = _inputs(kind, n, dtype)
+    got = run_gpu(kind, u0, co, T, mode="mwd", dw=dw, lanes=lanes)
+    _check(kind, u0, co, T, *got)
+
+
+@pytest.mark.parametrize("T", [0, 1, 2, 3, 4, 5, 8, 9])
+@pytest.mark.parametrize("cur", [0, 1])
+def test_mwd_step_counts_and_cur(T, cur):
+    """Clipping at t = T for every T mod h, and a run starting from buffer 1."""
+    n = (77, 30, 12)
+    print("mwd T", T, "cur", cur, flush=True)
+    u0, co = _inputs("7c", n, np.float64, seed=T + 3)
+    got = run_gpu("7c", u0, co, T, mode="mwd", dw=8, lanes=64, cur=cur)
+    uT, uTm1 = oracle.run("7c", u0, co, T)
+    assert np.array_equal(got[0], uT)
+    if T > 0:
+        assert np.array_equal(got[1], uTm1)
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (3, 2, 1), (1, 9, 4), (64, 1, 3), (200, 5, 2)])
+def test_mwd_degenerate_extents(n):
+    print("mwd degenerate", n, flush=True)
+    for kind in ("7c", "25c"):
+        u0, co = _inputs(kind, n, np.float64)
+        dw = 8 if kind == "7c" else 16
+        got = run_gpu(kind, u0, co, 6, mode="mwd", dw=dw, lanes=64)
+        _check(kind, u0, co, 6, *got)
+        got = run_gpu(kind, u0, co, 6, mode="naive")
+        _check(kind, u0, co, 6, *got)
+
+
+def test_wider_halo_than_radius():
+    n = (40, 20, 10)
+    print("halo 3 for 7v", flush=True)
+    u0 = gridgen.field(2, *n, 3, 0.0, 1.0)
+    u0[0:3, :, :] = 0.25   # non-zero boundary values
+    u0[:, :, -3:] = -0.5
+    co = gridgen.coeffs_7v(2, *n, 3)
+    for mode in ("naive", "mwd"):
+        got = run_gpu("7v", u0, co, 9, mode=mode, dw=8, lanes=64, halo=3)
+        uT, uTm1 = oracle.run("7v", u0, co, 9, halo=3)
+        assert np.array_equal(got[0], uT) and np.array_equal(got[1], uTm1)
+
+
+def test_workload1_7c_64cube_both_modes():
+    """The small 7-point workload: 64^3, T = 8, c0 = 0.4, c1 = 0.1, U[0,1)."""
+    w = gridgen.workloads()[1]
+    print("workload 1", flush=True)
+    u0 = gridgen.field(gridgen.seed_for_config(1), *w["n"], 1, *w["field"])
+    for mode, dw, lanes in (("naive", 0, 0), ("mwd", 8, 64), ("mwd", 8, 128), ("mwd", 4, 128)):
+        got = run_gpu("7c", u0, w["coeffs"], w["T"], mode=mode, dw=dw, lanes=lanes)
+        _check("7c", u0, w["coeffs"], w["T"], *got)
+
+
+def test_f32_against_f64_oracle_bound():
+    """FP32 form vs the FP64 oracle on the same (FP32-rounded) inputs:
+    ||e_T|| <= T (m + 1) u32 ||u_0|| for non-negative weights summing to <= 1."""
+    n = (96, 64, 32)
+    T = 20
+    print("f32 bound", flush=True)
+    u0 = gridgen.field(4, *n, 1, 0.0, 1.0).astype(np.float32)
+    C = [c.astype(np.float32) for c in gridgen.coeffs_7v(4, *n, 1)]
+    got, _ = run_gpu("7v", u0, C, T, mode="mwd", dw=8, lanes=128)
+    ref, _ = oracle.run("7v", u0.astype(np.float64), [c.astype(np.float64) for c in C], T)
+    err = np.max(np.abs(got.astype(np.float64) - ref))
+    assert err <= T * 14 * 2.0 ** -24 * float(np.max(u0))
