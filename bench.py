@@ -1,0 +1,226 @@
+"""Benchmark: GLUP/s of the MWD-blocked stencil sweep on one MI355X, against the
+naive one-sweep-per-step schedule, with the HBM roofline and the CPU oracle.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+                    [--mode auto|mwd|naive] [--dw D] [--lanes L]
+
+A step is one whole run of the hot path: T time steps of the workload's
+stencil over its grid (inputs resident in HBM), i.e. one stencil_run call.
+Each step continues from the previous one's result (the two-array state);
+values decay slowly (weights sum to <= 1) and stay far from subnormals.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4])
+    ap.add_argument("--dtype", default=None, help="for workload 3: f64 or f32")
+    ap.add_argument("--mode", default="auto", choices=["auto", "mwd", "naive"])
+    ap.add_argument("--dw", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--naive-steps", type=int, default=2)
+    ap.add_argument("--no-naive", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-T", type=int, default=0, help="time steps of the oracle sample")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def log(a, *msg):
+    if a.verbose:
+        print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(w, dtype, windex):
+    """Seeded inputs of a workload (recipe in gridgen)."""
+    import gridgen
+    nx, ny, nz = w["n"]
+    R = gridgen.RADIUS[w["kind"]]
+    seed = gridgen.seed_for_config(windex)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    u0 = gridgen.field(seed, nx, ny, nz, R, *w["field"], dtype=npdt)
+    if w["coeffs"] == "7v":
+        co = gridgen.coeffs_7v(seed, nx, ny, nz, R, dtype=npdt)
+    else:
+        co = list(w["coeffs"])
+    return u0, co
+
+
+def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, dw, lanes, halo):
+    """Run warmup + timed steps; return (seconds, plan description, profile)."""
+    a = u0_dev.clone()
+    b = u0_dev.clone()
+    g = S.make_grid(a, b, halo, 0)
+    if kind in ("7c", "25c"):
+        c = S.make_coeffs(kind, consts=co_dev)
+    else:
+        c = S.make_coeffs(kind, arrays=co_dev)
+    if mode == "auto":
+        plan = S.Plan(kind, dtype, *n)
+    else:
+        plan = S.Plan(kind, dtype, *n, mode=mode, dw=dw, lanes=lanes)
+    for _ in range(warmup):
+        plan.run(g, c, T)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_read()  # drop anything recorded so far
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(g, c, T)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = e0.elapsed_time(e1) / 1e3
+    prof = plan.profile_read()
+    desc = plan.describe()
+    state = (a, b)[g.cur]
+    plan.close()
+    return max(ev, 1e-9), wall, desc, prof, state
+
+
+def cpu_baseline(w, dtype, windex, T_cpu):
+    """Time the oracle (as it is) on the host cores on a bounded sample."""
+    import gridgen
+    import oracle
+    nx, ny, nz = w["n"]
+    R = gridgen.RADIUS[w["kind"]]
+    # a sample of the same workload: the full grid, fewer time steps
+    u0, co = make_inputs(w, dtype, windex)
+    threads = oracle.default_threads()
+    if os.environ.get("OMP_NUM_THREADS"):
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    t0 = time.perf_counter()
+    oracle.run(w["kind"], u0, co, T_cpu, halo=R, threads=threads)
+    dt = time.perf_counter() - t0
+    lups = nx * ny * nz * T_cpu
+    return {"value": lups / dt / 1e9, "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+            "sample": "%s, full %dx%dx%d grid, T=%d (of %d), %.1f s" % (
+                w["kind"] + "-" + dtype, nx, ny, nz, T_cpu, w["T"], dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported "
+                                   "(the multi-GPU design is described in DESIGN.md)" % a.gpus}))
+        return 2
+    import torch
+
+    import gridgen
+    import paper_1410_5561_amd as S
+
+    w = gridgen.workloads()[a.workload]
+    kind = w["kind"]
+    dtype = a.dtype or (w["dtype"] if isinstance(w["dtype"], str) else w["dtype"][0])
+    nx, ny, nz = w["n"]
+    T = w["T"]
+    R = gridgen.RADIUS[kind]
+    lups = nx * ny * nz * T
+    log(a, "inputs", w["name"], dtype)
+    u0, co = make_inputs(w, dtype, a.workload)
+    u0_dev = torch.from_numpy(u0).cuda()
+    if kind in ("7c", "25c"):
+        co_dev = co
+    else:
+        co_dev = [torch.from_numpy(c).cuda() for c in co]
+    del u0
+    co = None
+    log(a, "timing MWD")
+    sec, wall, desc, prof, state = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev, co_dev, T,
+                                             a.steps, a.warmup, a.mode, a.dw, a.lanes, R)
+    value = a.steps * lups / sec / 1e9
+    main_launches = max(1, prof["main_launches"])
+    model_bpl = desc["model_bytes_per_lup"]
+    # roofline of the dominant kernel: algorithmic bytes (model bytes/LUP x
+    # LUPs) over the time the tile kernels ran
+    alg_bytes_per_launch = model_bpl * lups * a.steps / main_launches
+    avg_launch_s = prof["main_ms"] / 1e3 / main_launches
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9
+    mode_name = {0: "auto", 1: "naive", 2: "mwd"}[desc["mode"]]
+    out = {
+        "metric": "GLUP/s + rocprof bytes/LUP, MWD vs naive sweep, FP64 and FP32, 1 GPU",
+        "value": round(value, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(sec * 1e3 / a.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": w["name"], "kind": kind, "nx": nx, "ny": ny, "nz": nz, "T": T,
+                   "lups_per_step": lups},
+        "schedule": {"mode": mode_name, "dw": desc["dw"], "lanes": desc["lanes"],
+                     "xtile": desc["xtile"], "levels": desc["levels"]},
+        "model_bytes_per_lup": round(model_bpl, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "mwd_row_kernel" if mode_name == "mwd" else "naive_sweep_kernel",
+                     "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "launches_per_step": prof["main_launches"] // a.steps,
+                     "other_kernels_ms_per_step": round(prof["other_ms"] / a.steps, 4)},
+    }
+    if not a.no_naive and mode_name != "naive":
+        log(a, "timing naive")
+        nsec, _, ndesc, nprof, _ = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev, co_dev, T,
+                                             a.naive_steps, 1, "naive", 0, 0, R)
+        nval = a.naive_steps * lups / nsec / 1e9
+        nb = ndesc["model_bytes_per_lup"]
+        out["naive"] = {"value": round(nval, 3), "unit": "GLUP/s",
+                        "ms_per_step": round(nsec * 1e3 / a.naive_steps, 3),
+                        "model_bytes_per_lup": nb,
+                        "achieved_GBs_at_model_bytes": round(nval * nb, 1)}
+        out["speedup_vs_naive"] = round(value / nval, 3)
+    # practical bandwidth reference: streaming copy of 2 GiB
+    nbytes = 1 << 31
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    S.stencil_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        S.stencil_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9
+    out["stream_copy_GBs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_stream_copy"] = round(achieved / copy_gbs, 4)
+    del src, dst
+    if not a.no_cpu_baseline:
+        log(a, "cpu baseline")
+        Tc = a.cpu_T or max(1, min(T, 8))
+        del state
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(w, dtype, a.workload, Tc)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

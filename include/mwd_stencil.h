@@ -162,6 +162,25 @@ int stencil_plan_describe(const stencil_plan *plan, stencil_plan_desc *out);
  * arguments. */
 double stencil_model_bytes_per_lup(int32_t kind, int32_t dtype, int32_t dw);
 
+/* Kernel timing for measurement tools.  While enabled, the plan records a HIP
+ * event pair on the run's stream around every kernel it launches.
+ * stencil_profile_read waits for those events and returns
+ *   out[0] = summed milliseconds of the sweep / MWD tile kernels,
+ *   out[1] = their launch count,
+ *   out[2] = summed milliseconds of the plan's other kernels (the final
+ *            gather of the MWD scratch pairs), out[3] = their count,
+ * accumulated since the previous read, then forgets them. */
+int stencil_profile_enable(stencil_plan *plan, int32_t enable);
+int stencil_profile_read(stencil_plan *plan, double out[4]);
+
+/* Streaming device-to-device copy of `bytes` bytes (a multiple of 16; both
+ * pointers 16-byte aligned device memory, not overlapping), asynchronous on
+ * `stream`.  It is the practical-bandwidth reference, the analogue of the
+ * STREAM COPY figure the paper measures its memory bound with (Sec. IV-A),
+ * and the kernel of known traffic used to calibrate HBM byte counters.
+ * Errors: EINVAL (NULL, misaligned, size not a multiple of 16), EDEVICE. */
+int stencil_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
 const char *stencil_strerror(int code);
 const char *stencil_last_error(void);  /* thread-local detail of the last failure */
 int stencil_abi_version(void);

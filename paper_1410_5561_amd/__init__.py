@@ -16,7 +16,8 @@ __all__ = [
     "stencil_create", "stencil_run", "stencil_destroy", "stencil_run_batched",
     "stencil_norms", "stencil_diff_norms", "stencil_plan_describe",
     "stencil_model_bytes_per_lup", "stencil_strerror", "stencil_last_error",
-    "stencil_abi_version", "Plan", "make_grid", "make_coeffs", "padded_empty", "radius",
+    "stencil_abi_version", "stencil_profile_enable", "stencil_profile_read",
+    "stencil_stream_copy", "Plan", "make_grid", "make_coeffs", "padded_empty", "radius",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +84,10 @@ _SIGS = {
     "stencil_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stencil_last_error": (ctypes.c_char_p, []),
     "stencil_abi_version": (ctypes.c_int, []),
+    "stencil_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "stencil_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "stencil_stream_copy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p]),
 }
 
 
@@ -186,6 +191,22 @@ def stencil_diff_norms(a: StencilGrid, b: StencilGrid, stream=None) -> tuple[flo
     return out[0], out[1]
 
 
+def stencil_profile_enable(plan, enable: bool = True):
+    _check(lib().stencil_profile_enable(plan, 1 if enable else 0), "stencil_profile_enable")
+
+
+def stencil_profile_read(plan) -> dict:
+    out = (ctypes.c_double * 4)()
+    _check(lib().stencil_profile_read(plan, out), "stencil_profile_read")
+    return {"main_ms": out[0], "main_launches": int(out[1]),
+            "other_ms": out[2], "other_launches": int(out[3])}
+
+
+def stencil_stream_copy(dst, src, nbytes: int, stream=None):
+    _check(lib().stencil_stream_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), int(nbytes),
+                                     _stream_ptr(stream)), "stencil_stream_copy")
+
+
 def stencil_plan_describe(plan) -> dict:
     d = StencilPlanDesc()
     _check(lib().stencil_plan_describe(plan, ctypes.byref(d)), "stencil_plan_describe")
@@ -210,6 +231,12 @@ class Plan:
 
     def describe(self) -> dict:
         return stencil_plan_describe(self.ptr)
+
+    def profile(self, enable: bool = True):
+        stencil_profile_enable(self.ptr, enable)
+
+    def profile_read(self) -> dict:
+        return stencil_profile_read(self.ptr)
 
     def close(self):
         if self.ptr:

@@ -110,6 +110,7 @@ struct stencil_plan {
     long long scratch_sy, scratch_sz;
     int scratch_halo, scratch_dev;
     BatchState* batch;
+    Prof* prof;
 };
 
 static void free_scratch(stencil_plan* p)
@@ -241,6 +242,11 @@ int stencil_destroy(stencil_plan* p)
     (void)hipDeviceSynchronize();
     free_scratch(p);
     batch_free(p->batch);
+    if (p->prof) {
+        double tmp[4];
+        (void)p->prof->collect(tmp);
+        delete p->prof;
+    }
     delete p;
     return STENCIL_OK;
 }
@@ -272,13 +278,15 @@ int stencil_run(stencil_plan* p, stencil_grid* g, const stencil_coeffs* c, int32
     DevGrid d = to_dev(g);
     if (p->mode == STENCIL_MODE_NAIVE) {
         for (int t = 0; t < T; ++t) {
+            if (p->prof) p->prof->begin(s);
             hipError_t e = naive_sweep(d, w, d.org[(d.cur + t) & 1], d.org[(d.cur + t + 1) & 1], s);
+            if (p->prof) p->prof->end(s, 0);
             if (e != hipSuccess) return hip_fail(e, "naive sweep launch");
         }
     } else {
         rc = ensure_scratch(p, g);
         if (rc) return rc;
-        hipError_t e = mwd_run(d, w, T, p->shape, p->scratch_org, s);
+        hipError_t e = mwd_run(d, w, T, p->shape, p->scratch_org, s, p->prof);
         if (e != hipSuccess) return hip_fail(e, "MWD launch");
     }
     g->cur ^= (T & 1);
@@ -301,6 +309,33 @@ int stencil_plan_describe(const stencil_plan* p, stencil_plan_desc* out)
     } else if (p->kind != STENCIL_KIND_MIXED) {
         out->model_bytes_per_lup = stencil_model_bytes_per_lup(p->kind, p->dtype, 0);
     }
+    return STENCIL_OK;
+}
+
+int stencil_profile_enable(stencil_plan* p, int32_t enable)
+{
+    if (!p) return fail(STENCIL_EINVAL, "plan is NULL");
+    if (enable) {
+        if (!p->prof) {
+            p->prof = new (std::nothrow) Prof();
+            if (!p->prof) return fail(STENCIL_ENOMEM, "profiler allocation failed");
+        }
+        p->prof->on = true;
+    } else if (p->prof) {
+        p->prof->on = false;
+    }
+    return STENCIL_OK;
+}
+
+int stencil_profile_read(stencil_plan* p, double out[4])
+{
+    if (!p || !out) return fail(STENCIL_EINVAL, "NULL argument");
+    if (!p->prof) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return STENCIL_OK;
+    }
+    hipError_t e = p->prof->collect(out);
+    if (e != hipSuccess) return hip_fail(e, "profile events");
     return STENCIL_OK;
 }
 
@@ -329,6 +364,17 @@ int stencil_diff_norms(const stencil_grid* a, const stencil_grid* b, double out[
     DevGrid da = to_dev(a), db = to_dev(b);
     hipError_t e = norms_fp64(da, da.org[da.cur], db, db.org[db.cur], 1, out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "diff norms");
+    return STENCIL_OK;
+}
+
+int stencil_stream_copy(void* dst, const void* src, int64_t bytes, void* stream)
+{
+    if (!dst || !src) return fail(STENCIL_EINVAL, "NULL pointer");
+    if (bytes < 0 || bytes % 16) return fail(STENCIL_EINVAL, "size must be a non-negative multiple of 16");
+    if ((reinterpret_cast<uintptr_t>(dst) % 16) || (reinterpret_cast<uintptr_t>(src) % 16))
+        return fail(STENCIL_EINVAL, "pointers must be 16-byte aligned");
+    hipError_t e = stream_copy(dst, src, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "stream copy");
     return STENCIL_OK;
 }
 

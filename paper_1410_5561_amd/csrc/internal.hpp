@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace mwd {
 
@@ -32,6 +33,50 @@ struct HostWeights {
     const void* org[13];
 };
 
+// Optional timing of every kernel a plan launches: an event pair around each
+// launch on the launch stream (class 0: the sweep / MWD tile kernels, class 1:
+// everything else).  Used by measurement tools through the ABI.
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> start, stop;
+    std::vector<int> cls;
+    hipEvent_t pending = nullptr;
+    void begin(hipStream_t s) {
+        if (!on) return;
+        pending = nullptr;
+        if (hipEventCreate(&pending) == hipSuccess) (void)hipEventRecord(pending, s);
+    }
+    void end(hipStream_t s, int c) {
+        if (!on || !pending) return;
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, s);
+        start.push_back(pending);
+        stop.push_back(e);
+        cls.push_back(c);
+        pending = nullptr;
+    }
+    // Sum elapsed ms and counts per class, then release the events.
+    hipError_t collect(double out[4]) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        hipError_t err = hipSuccess;
+        for (size_t i = 0; i < start.size(); ++i) {
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(stop[i]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, start[i], stop[i]);
+            if (e != hipSuccess) err = e;
+            out[2 * cls[i]] += ms;
+            out[2 * cls[i] + 1] += 1.0;
+            (void)hipEventDestroy(start[i]);
+            (void)hipEventDestroy(stop[i]);
+        }
+        start.clear();
+        stop.clear();
+        cls.clear();
+        return err;
+    }
+};
+
 // One full sweep: dst <- op(src) over the interior.
 hipError_t naive_sweep(const DevGrid& g, const HostWeights& w, const void* src, void* dst,
                        hipStream_t stream);
@@ -51,11 +96,13 @@ int mwd_xtile(int kind, const MwdShape& s);
 // Run T steps with MWD.  `scratch` holds two extra grid-sized buffer pairs
 // (4 pointers at the interior origin, same strides as g).
 hipError_t mwd_run(const DevGrid& g, const HostWeights& w, int T, const MwdShape& s,
-                   void* const scratch[4], hipStream_t stream);
+                   void* const scratch[4], hipStream_t stream, Prof* prof);
 
 // FP64 norms: which 0 -> of a, which 1 -> of a - b (b may be another dtype).
 hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b,
                       int which, double out[2], hipStream_t stream);
+
+hipError_t stream_copy(void* dst, const void* src, long long bytes, hipStream_t stream);
 
 void set_last_error(const std::string& s);
 

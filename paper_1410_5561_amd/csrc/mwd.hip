@@ -39,11 +39,11 @@ int mwd_levels(int kind, const MwdShape& s) { return s.dw / radius_of(kind) - 1;
 int mwd_xtile(int kind, const MwdShape& s) { return 64 * s.wpr - 2 * mwd_levels(kind, s) * radius_of(kind); }
 
 hipError_t mwd_run(const DevGrid& g, const HostWeights& w, int T, const MwdShape& s,
-                   void* const scratch[4], hipStream_t stream)
+                   void* const scratch[4], hipStream_t stream, Prof* prof)
 {
     const MwdEntry* e = find_entry(w.kind, g.dtype, s);
     if (!e) return hipErrorInvalidValue;
-    return e->fn(g, w, T, scratch, stream);
+    return e->fn(g, w, T, scratch, stream, prof);
 }
 
 }  // namespace mwd

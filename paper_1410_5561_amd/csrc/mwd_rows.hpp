@@ -44,7 +44,7 @@ mwd_gather_kernel(MwdArgs<T> a)
 
 template <int K, typename T, int DW, int WPR>
 static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, void* const scratch[4],
-                           hipStream_t stream)
+                           hipStream_t stream, Prof* prof)
 {
     using G = MwdGeom<K, DW, WPR>;
     MwdArgs<T> a{};
@@ -76,16 +76,20 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         const int yoff = (rho % 2) * (DW / 2);
         a.ybase = yoff > 0 ? yoff - DW : 0;
         const int nB = (g.ny - 1 - a.ybase) / DW + 1;
+        if (prof) prof->begin(stream);
         hipLaunchKernelGGL((mwd_row_kernel<K, T, DW, WPR>), dim3(nB * a.nxt), dim3(G::NT), 0, stream, a);
+        if (prof) prof->end(stream, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     dim3 gg((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    if (prof) prof->begin(stream);
     hipLaunchKernelGGL((mwd_gather_kernel<T, G::R, DW>), gg, dim3(256), 0, stream, a);
+    if (prof) prof->end(stream, 1);
     return hipGetLastError();
 }
 
-using RunFn = hipError_t (*)(const DevGrid&, const HostWeights&, int, void* const*, hipStream_t);
+using RunFn = hipError_t (*)(const DevGrid&, const HostWeights&, int, void* const*, hipStream_t, Prof*);
 
 struct MwdEntry {
     int kind, dtype, dw, wpr;
