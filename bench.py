@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-T", type=int, default=0, help="time steps of the oracle sample")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time every compiled MWD shape (diamond width x lanes)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -196,6 +198,23 @@ def main():
                         "model_bytes_per_lup": nb,
                         "achieved_GBs_at_model_bytes": round(nval * nb, 1)}
         out["speedup_vs_naive"] = round(value / nval, 3)
+    if a.sweep:
+        shapes = {1: [(4, 64), (4, 128), (8, 64), (8, 128), (16, 64)],
+                  4: [(8, 64), (16, 64)]}[R]
+        sw = []
+        for dw, lx in shapes:
+            try:
+                ssec, _, sdesc, sprof, _ = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev,
+                                                     co_dev, T, 2, 1, "mwd", dw, lx, R)
+            except Exception as e:  # shape not compiled for this dtype
+                sw.append({"dw": dw, "lanes": lx, "error": str(e)[:80]})
+                continue
+            sv = 2 * lups / ssec / 1e9
+            sw.append({"dw": dw, "lanes": lx, "xtile": sdesc["xtile"], "GLUPs": round(sv, 2),
+                       "model_bytes_per_lup": round(sdesc["model_bytes_per_lup"], 3),
+                       "GBs_at_model": round(sv * sdesc["model_bytes_per_lup"], 1)})
+            log(a, "sweep", sw[-1])
+        out["sweep"] = sw
     # practical bandwidth reference: streaming copy of 2 GiB
     nbytes = 1 << 31
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")

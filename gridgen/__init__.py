@@ -52,17 +52,43 @@ def _stream(seed: int, offset: int) -> np.random.Generator:
     return np.random.Generator(bg)
 
 
+def _workers() -> int:
+    import os
+    n = len(os.sched_getaffinity(0))
+    return max(1, min(16, n))
+
+
+def _slabs(nz: int, slab: int):
+    return [(z0, min(nz, z0 + slab)) for z0 in range(0, nz, slab)]
+
+
+def _parallel(fn, items):
+    """Run fn over items in threads (NumPy's generators release the GIL);
+    each slab draws from its own offset of the stream, so the result does
+    not depend on the thread count."""
+    if len(items) <= 1:
+        for it in items:
+            fn(it)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(fn, items))
+
+
 def uniform_into(out: np.ndarray, seed: int, offset: int, lo: float, hi: float,
                  slab: int = 16) -> None:
     """Fill ``out`` (shape (nz, ny, nx), any float dtype) with U[lo, hi) draws
     number offset, offset+1, ... of stream ``seed`` in C order, slab by slab."""
     nz, ny, nx = out.shape
     plane = ny * nx
-    for z0 in range(0, nz, slab):
-        z1 = min(nz, z0 + slab)
+
+    def one(zz):
+        z0, z1 = zz
         g = _stream(seed, offset + z0 * plane)
         d = g.random((z1 - z0) * plane).reshape(z1 - z0, ny, nx)
         out[z0:z1] = lo + (hi - lo) * d
+
+    _parallel(one, _slabs(nz, slab))
 
 
 def field(seed: int, nx: int, ny: int, nz: int, halo: int, lo: float, hi: float,
@@ -89,8 +115,9 @@ def coeffs_7v(seed: int, nx: int, ny: int, nz: int, halo: int, dtype=np.float64,
     for a in arrs:
         a[...] = 0
     views = [interior(a, halo) for a in arrs]
-    for z0 in range(0, nz, slab):
-        z1 = min(nz, z0 + slab)
+
+    def one(zz):
+        z0, z1 = zz
         cnt = (z1 - z0) * plane
         raw = []
         for m in range(7):
@@ -101,6 +128,8 @@ def coeffs_7v(seed: int, nx: int, ny: int, nz: int, halo: int, dtype=np.float64,
             s = s + raw[m]
         for m in range(7):
             views[m][z0:z1] = (total * raw[m]) / s
+
+    _parallel(one, _slabs(nz, slab))
     return arrs
 
 

@@ -1,18 +1,353 @@
+// Host side of the batched form: tile table, per-grid shapes, scratch, the
+// captured hipGraph and its replay.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "batch.hpp"
+#include "batch_variants.hpp"
 #include "internal.hpp"
+#include "tune.hpp"
 
 namespace mwd {
 
-struct BatchState {
-    int dummy;
-};
+int check_grid(const stencil_grid* g, const char* name);
+DevGrid to_dev(const stencil_grid* g);
+int check_coeffs(const stencil_coeffs* c, int kind, const stencil_grid* g, HostWeights* out);
 
-int batch_run(int, int, BatchState**, stencil_grid*, const stencil_coeffs*, int, int, hipStream_t)
+__global__ void batch_reset_kernel(int* done, int ngrids, int* counter, int* err)
 {
-    set_last_error("batched runs are not built yet");
-    return STENCIL_EUNSUPPORTED;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ngrids) done[i] = 0;
+    if (i == 0) {
+        *counter = 0;
+        *err = 0;
+    }
 }
 
-void batch_free(BatchState* s) { delete s; }
+hipError_t batch_reset(int* done, int ngrids, int* counter, int* err, hipStream_t s)
+{
+    const int n = ngrids > 0 ? ngrids : 1;
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, done, ngrids, counter, err);
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu_f64();
+int batch_blocks_per_cu_f32();
+int batch_blocks_per_cu(int dtype) { return dtype == 0 ? batch_blocks_per_cu_f64() : batch_blocks_per_cu_f32(); }
+
+struct BatchKey {
+    std::vector<uintptr_t> ptrs;
+    std::vector<long long> dims;
+    int T, dtype;
+    bool operator==(const BatchKey& o) const {
+        return T == o.T && dtype == o.dtype && ptrs == o.ptrs && dims == o.dims;
+    }
+};
+
+struct BatchGraph {
+    BatchKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* dev = nullptr;        // tiles | gargs | gvariant | done | counter | err
+    void* scratch = nullptr;    // two extra buffer pairs per grid
+    int* err = nullptr;
+    int ntiles = 0;
+    std::vector<int> variants;  // chosen variant per grid (for reporting)
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (dev) (void)hipFree(dev);
+        if (scratch) (void)hipFree(scratch);
+        exec = nullptr;
+        graph = nullptr;
+        dev = scratch = nullptr;
+    }
+};
+
+struct BatchState {
+    std::vector<BatchGraph> cache;  // at most two: runs with odd T alternate cur
+};
+
+static size_t es_of(int dtype) { return dtype == 0 ? 8 : 4; }
+
+static int variant_index(int kind, int dtype, const MwdShape& s)
+{
+    const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
+    for (int i = 0; i < nv; ++i)
+        if (kBatchVariantInfo[i].kind == kind && kBatchVariantInfo[i].dw == s.dw && kBatchVariantInfo[i].wpr == s.wpr)
+            return i;
+    return -1;
+}
+
+template <typename T>
+static void fill_args(MwdArgs<T>& a, const DevGrid& d, const HostWeights& w, T* const pr[4], int T_steps)
+{
+    std::memset(&a, 0, sizeof(a));
+    a.pair[0][0] = static_cast<T*>(d.org[0]);
+    a.pair[0][1] = static_cast<T*>(d.org[1]);
+    a.pair[1][0] = pr[0];
+    a.pair[1][1] = pr[1];
+    a.pair[2][0] = pr[2];
+    a.pair[2][1] = pr[3];
+    a.halo = static_cast<const T*>(d.org[d.cur]);
+    for (int m = 0; m < 13; ++m) {
+        a.w.c[m] = static_cast<T>(w.c[m]);
+        a.w.arr[m] = static_cast<const T*>(w.org[m]);
+    }
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.nz = d.nz;
+    a.sy = d.sy;
+    a.sz = d.sz;
+    a.cur = d.cur;
+    a.nsteps = T_steps;
+}
+
+template <typename T>
+static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* hw, int n, int T_steps,
+                       int dtype, std::string* errmsg)
+{
+    // 1. shape per grid (autotuned per kind and size bucket)
+    std::vector<int> var(n);
+    for (int i = 0; i < n; ++i) {
+        MwdShape s = tune_batch_shape(hw[i].kind, dtype, grids[i].nx, grids[i].ny, grids[i].nz, T_steps);
+        int v = variant_index(hw[i].kind, dtype, s);
+        if (v < 0) {
+            *errmsg = "no batched tile shape for kind " + std::to_string(hw[i].kind);
+            return STENCIL_EUNSUPPORTED;
+        }
+        var[i] = v;
+    }
+    // 2. scratch: two extra pairs per grid, each laid out like the grid
+    std::vector<size_t> soff(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        const size_t bytes = (size_t)grids[i].sz * (size_t)(grids[i].nz + 2 * grids[i].halo) * es_of(dtype);
+        const size_t aligned = (bytes + 255) & ~size_t(255);
+        soff[i + 1] = soff[i] + 4 * aligned;
+    }
+    if (hipMalloc(&bg.scratch, soff[n] ? soff[n] : 256) != hipSuccess) {
+        (void)hipGetLastError();
+        bg.scratch = nullptr;
+        *errmsg = "batched scratch allocation of " + std::to_string(soff[n]) + " bytes failed";
+        return STENCIL_ENOMEM;
+    }
+    // 3. tile table, rows of all grids interleaved row by row (topological)
+    std::vector<MwdArgs<T>> gargs(n);
+    std::vector<BatchTile> tiles;
+    std::vector<int> rows(n), nxt(n), nrow_tiles_done(n, 0);
+    int max_rows = 0;
+    for (int i = 0; i < n; ++i) {
+        const BatchVariantInfo& vi = kBatchVariantInfo[var[i]];
+        const MwdShape s{vi.dw, vi.wpr};
+        const int R = radius_of(vi.kind), H = vi.dw / (2 * R);
+        const int XT = mwd_xtile(vi.kind, s);
+        DevGrid d = to_dev(&grids[i]);
+        const size_t es = es_of(dtype);
+        const size_t bytes = (soff[i + 1] - soff[i]) / 4;
+        const long long off = (long long)d.halo * d.sz + (long long)d.halo * d.sy + d.halo;
+        T* pr[4];
+        for (int k = 0; k < 4; ++k)
+            pr[k] = reinterpret_cast<T*>(static_cast<char*>(bg.scratch) + soff[i] + k * bytes + off * es);
+        fill_args<T>(gargs[i], d, hw[i], pr, T_steps);
+        nxt[i] = (d.nx + XT - 1) / XT;
+        gargs[i].nxt = nxt[i];
+        rows[i] = (T_steps + H - 1) / H + 1;  // rows 0 .. rho_max
+        max_rows = std::max(max_rows, rows[i] + 1);  // + the gather "row"
+    }
+    for (int rho = 0; rho < max_rows; ++rho) {
+        // larger grids first within a row: better tail balance
+        std::vector<int> order;
+        for (int i = 0; i < n; ++i)
+            if (rho <= rows[i]) order.push_back(i);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return (long long)grids[a].nx * grids[a].ny * grids[a].nz > (long long)grids[b].nx * grids[b].ny * grids[b].nz;
+        });
+        for (int i : order) {
+            const BatchVariantInfo& vi = kBatchVariantInfo[var[i]];
+            const int R = radius_of(vi.kind), H = vi.dw / (2 * R);
+            if (rho < rows[i]) {
+                const int yoff = (rho % 2) * (vi.dw / 2);
+                const int ybase = yoff > 0 ? yoff - vi.dw : 0;
+                const int nB = (grids[i].ny - 1 - ybase) / vi.dw + 1;
+                const int need = nrow_tiles_done[i];
+                for (int b = 0; b < nB; ++b)
+                    for (int j = 0; j < nxt[i]; ++j)
+                        tiles.push_back(BatchTile{i, var[i], rho, (rho - 1) * H, ybase, b, j, need});
+                nrow_tiles_done[i] += nB * nxt[i];
+            } else {
+                // gather after the last row, in chunks of planes
+                const int need = nrow_tiles_done[i];
+                const int zc = std::max(1, (int)(65536 / std::max(1LL, (long long)grids[i].nx * grids[i].ny)));
+                for (int z0 = 0; z0 < grids[i].nz; z0 += zc)
+                    tiles.push_back(BatchTile{i, kGatherVariant, -1, 0, 0, z0, std::min(zc, grids[i].nz - z0), need});
+            }
+        }
+    }
+    // 4. device tables
+    const size_t tb = tiles.size() * sizeof(BatchTile);
+    const size_t ab = (size_t)n * sizeof(MwdArgs<T>);
+    const size_t vb = (size_t)n * sizeof(int);
+    const size_t db = (size_t)n * sizeof(int);
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t total = al(tb) + al(ab) + al(vb) + al(db) + 256 + 256;
+    if (hipMalloc(&bg.dev, total) != hipSuccess) {
+        (void)hipGetLastError();
+        bg.dev = nullptr;
+        *errmsg = "batched table allocation failed";
+        return STENCIL_ENOMEM;
+    }
+    char* base = static_cast<char*>(bg.dev);
+    BatchTile* d_tiles = reinterpret_cast<BatchTile*>(base);
+    MwdArgs<T>* d_args = reinterpret_cast<MwdArgs<T>*>(base + al(tb));
+    int* d_var = reinterpret_cast<int*>(base + al(tb) + al(ab));
+    int* d_done = reinterpret_cast<int*>(base + al(tb) + al(ab) + al(vb));
+    int* d_counter = reinterpret_cast<int*>(base + al(tb) + al(ab) + al(vb) + al(db));
+    int* d_err = reinterpret_cast<int*>(base + al(tb) + al(ab) + al(vb) + al(db) + 256);
+    hipError_t e = hipMemcpy(d_tiles, tiles.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_args, gargs.data(), ab, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_var, var.data(), vb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        *errmsg = std::string("batched table upload: ") + hipGetErrorString(e);
+        return STENCIL_EDEVICE;
+    }
+    bg.err = d_err;
+    bg.ntiles = (int)tiles.size();
+    bg.variants = var;
+    // 5. capture: reset counters, then the persistent kernel
+    int dev = 0, ncu = 0, wall_khz = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
+    if (ncu <= 0) ncu = 256;
+    if (wall_khz <= 0) wall_khz = 100000;
+    const int nblocks = std::max(1, std::min(bg.ntiles, ncu * batch_blocks_per_cu(dtype)));
+    BatchLaunch<T> L{d_tiles, bg.ntiles, d_args, d_var, d_done, d_counter, d_err,
+                     (long long)wall_khz * 1000LL * 4};  // a dependency wait gives up after 4 s
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        *errmsg = std::string("stream: ") + hipGetErrorString(e);
+        return STENCIL_EDEVICE;
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = batch_reset(d_done, n, d_counter, d_err, cs);
+        hipError_t e2;
+        if constexpr (sizeof(T) == 8) e2 = batch_launch_f64(L, nblocks, cs);
+        else e2 = batch_launch_f32(L, nblocks, cs);
+        e = hipStreamEndCapture(cs, &bg.graph);
+        if (e == hipSuccess && e1 != hipSuccess) e = e1;
+        if (e == hipSuccess && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        *errmsg = std::string("graph capture: ") + hipGetErrorString(e);
+        return STENCIL_EDEVICE;
+    }
+    return STENCIL_OK;
+}
+
+int batch_run(int plan_kind, int plan_dtype, BatchState** state, stencil_grid* grids, const stencil_coeffs* coeffs,
+              int n, int T, hipStream_t stream)
+{
+    if (!grids || !coeffs || n < 1) {
+        set_last_error("batched run needs n >= 1 grids and coefficients");
+        return STENCIL_EINVAL;
+    }
+    if (T < 0) {
+        set_last_error("T < 0");
+        return STENCIL_EINVAL;
+    }
+    std::vector<HostWeights> hw(n);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_grid(&grids[i], "grids[i]");
+        if (rc) return rc;
+        if (grids[i].dtype != plan_dtype) {
+            set_last_error("grid dtype differs from the plan's");
+            return STENCIL_EINVAL;
+        }
+        const int kind = coeffs[i].kind;
+        if (kind < 0 || kind > 3 || (plan_kind != STENCIL_KIND_MIXED && kind != plan_kind)) {
+            set_last_error("grid kind not allowed by the plan");
+            return STENCIL_EINVAL;
+        }
+        if (grids[i].halo < radius_of(kind)) {
+            set_last_error("halo narrower than the stencil radius");
+            return STENCIL_EINVAL;
+        }
+        rc = check_coeffs(&coeffs[i], kind, &grids[i], &hw[i]);
+        if (rc) return rc;
+    }
+    if (T == 0) return STENCIL_OK;
+    BatchKey key;
+    key.T = T;
+    key.dtype = plan_dtype;
+    for (int i = 0; i < n; ++i) {
+        key.ptrs.push_back((uintptr_t)grids[i].buf[0]);
+        key.ptrs.push_back((uintptr_t)grids[i].buf[1]);
+        for (int m = 0; m < 13; ++m) key.ptrs.push_back((uintptr_t)coeffs[i].arr[m]);
+        long long dims[] = {grids[i].nx, grids[i].ny, grids[i].nz, grids[i].halo, grids[i].sy, grids[i].sz,
+                            grids[i].cur, coeffs[i].kind};
+        key.dims.insert(key.dims.end(), dims, dims + 8);
+        for (int m = 0; m < 13; ++m) {
+            long long bits;
+            std::memcpy(&bits, &coeffs[i].c[m], sizeof(bits));
+            key.dims.push_back(bits);
+        }
+    }
+    if (!*state) *state = new BatchState();
+    BatchState* st = *state;
+    BatchGraph* bg = nullptr;
+    for (auto& c : st->cache)
+        if (c.key == key) bg = &c;
+    if (!bg) {
+        if (st->cache.size() >= 2) {
+            st->cache.front().release();
+            st->cache.erase(st->cache.begin());
+        }
+        st->cache.emplace_back();
+        bg = &st->cache.back();
+        bg->key = key;
+        std::string msg;
+        int rc = plan_dtype == 0 ? build_graph<double>(*bg, grids, hw.data(), n, T, plan_dtype, &msg)
+                                 : build_graph<float>(*bg, grids, hw.data(), n, T, plan_dtype, &msg);
+        if (rc) {
+            bg->release();
+            st->cache.pop_back();
+            set_last_error(msg);
+            return rc;
+        }
+    }
+    hipError_t e = hipGraphLaunch(bg->exec, stream);
+    if (e != hipSuccess) {
+        set_last_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        return STENCIL_EDEVICE;
+    }
+    // the launch is synchronous towards the caller: wait, then check that no
+    // dependency wait gave up
+    int herr = 0;
+    e = hipMemcpyAsync(&herr, bg->err, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        set_last_error(std::string("batched run: ") + hipGetErrorString(e));
+        return STENCIL_EDEVICE;
+    }
+    if (herr) {
+        set_last_error("a batched tile's dependency wait timed out");
+        return STENCIL_EDEVICE;
+    }
+    for (int i = 0; i < n; ++i) grids[i].cur ^= (T & 1);
+    return STENCIL_OK;
+}
+
+void batch_free(BatchState* s)
+{
+    if (!s) return;
+    for (auto& c : s->cache) c.release();
+    delete s;
+}
 
 }  // namespace mwd

@@ -82,7 +82,7 @@ __device__ __forceinline__ T apply_stencil(const NB& nb, const WF& w) {
 template <typename T>
 struct Weights {
     T c[13];
-    const T* __restrict__ arr[13];
+    const T* arr[13];
 };
 
 }  // namespace mwd

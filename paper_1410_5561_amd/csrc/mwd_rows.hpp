@@ -10,13 +10,13 @@ namespace mwd {
 
 template <int K, typename T, int DW, int WPR>
 __global__ void __launch_bounds__(64 * DW * WPR)
-mwd_row_kernel(MwdArgs<T> a)
+mwd_row_kernel(MwdArgs<T> a, MwdRow row)
 {
     using G = MwdGeom<K, DW, WPR>;
     __shared__ T ex[2][G::L][G::NS][G::LX];
     const int b = blockIdx.x / a.nxt;
     const int j = blockIdx.x % a.nxt;
-    mwd_tile<K, T, DW, WPR>(a, b, j, ex);
+    mwd_tile<K, T, DW, WPR>(a, row, b, j, ex);
 }
 
 // After the last row, copy u_T and u_{T-1} of every point out of the pair
@@ -71,13 +71,14 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
     a.nxt = (g.nx + G::XT - 1) / G::XT;
     const int rho_max = (nsteps + G::H - 1) / G::H;
     for (int rho = 0; rho <= rho_max; ++rho) {
-        a.rho = rho;
-        a.t0 = (rho - 1) * G::H;
+        MwdRow row;
+        row.rho = rho;
+        row.t0 = (rho - 1) * G::H;
         const int yoff = (rho % 2) * (DW / 2);
-        a.ybase = yoff > 0 ? yoff - DW : 0;
-        const int nB = (g.ny - 1 - a.ybase) / DW + 1;
+        row.ybase = yoff > 0 ? yoff - DW : 0;
+        const int nB = (g.ny - 1 - row.ybase) / DW + 1;
         if (prof) prof->begin(stream);
-        hipLaunchKernelGGL((mwd_row_kernel<K, T, DW, WPR>), dim3(nB * a.nxt), dim3(G::NT), 0, stream, a);
+        hipLaunchKernelGGL((mwd_row_kernel<K, T, DW, WPR>), dim3(nB * a.nxt), dim3(G::NT), 0, stream, a, row);
         if (prof) prof->end(stream, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -72,14 +72,18 @@ struct MwdArgs {
     long long sy, sz;
     int cur;              // level t lives in buffer (cur + t) & 1 of its pair
     int nsteps;           // total number of time steps of the run
+    int nxt;              // x tiles per diamond
+};
+
+// One diamond row of the schedule.
+struct MwdRow {
     int rho, t0;          // row index and the level just below the row's tiles
     int ybase;            // yL of the row's first diamond
-    int nxt;              // x tiles per diamond
 };
 
 // The tile (diamond b of the row, x tile j) computed by one workgroup.
 template <int K, typename T, int DW, int WPR>
-__device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, int b, int j,
+__device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row, int b, int j,
                                          T (*ex)[MwdGeom<K, DW, WPR>::L][MwdGeom<K, DW, WPR>::NS]
                                               [MwdGeom<K, DW, WPR>::LX])
 {
@@ -89,9 +93,12 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, int b, int j,
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    // Waves beyond this tile shape's count (when the workgroup is sized for a
+    // larger shape, as in the batched kernel) only take part in the barriers.
+    const bool wave_active = wave < G::NWAVES;
     const int yr = wave / WPR;
     const int xl = (wave % WPR) * 64 + lane;
-    const int yL = a.ybase + b * DW;
+    const int yL = row.ybase + b * DW;
     const int x0 = j * XT;
     const int x = x0 - L * R + xl;
     const int y = yL + yr;
@@ -104,7 +111,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, int b, int j,
     // domain and to 1 <= t <= T)?  Wave-uniform.
     auto computed = [&](int yrr, int tau) -> bool {
         if (tau < 1 || tau > L || yrr < 0 || yrr >= DW) return false;
-        const int t = a.t0 + tau;
+        const int t = row.t0 + tau;
         if (t < 1 || t > a.nsteps) return false;
         const int yy = yL + yrr;
         if (yy < 0 || yy >= a.ny) return false;
@@ -133,22 +140,23 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, int b, int j,
     }
     for (int tau = 0; tau <= L; ++tau)
         if (((cmask >> tau) & 1u) && tau >= thi - 1) smask |= 1u << tau;
+    if (!wave_active) cmask = pmask = smask = 0u;
     cmask = __builtin_amdgcn_readfirstlane(cmask);
     pmask = __builtin_amdgcn_readfirstlane(pmask);
     smask = __builtin_amdgcn_readfirstlane(smask);
 
     const T* src[L + 1];
     T* dst[L + 1];
-    T* const* outp = a.pair[pair_of_row(a.rho)];
+    T* const* outp = a.pair[pair_of_row(row.rho)];
 #pragma unroll
     for (int tau = 0; tau <= L; ++tau) {
-        src[tau] = level_src(y, a.t0 + tau);
-        dst[tau] = outp[(a.cur + a.t0 + tau) & 1];
+        src[tau] = level_src(y, row.t0 + tau);
+        dst[tau] = outp[(a.cur + row.t0 + tau) & 1];
     }
 
     // Side rows: R rows beyond each edge of the diamond, needed only at level
     // h - 1 by the widest level h; loaded by the edge waves straight into LDS.
-    const bool left_edge = yr == 0, right_edge = yr == DW - 1;
+    const bool left_edge = wave_active && yr == 0, right_edge = wave_active && yr == DW - 1;
     const bool side_wave = left_edge || right_edge;
     bool sv_present[R];
     const T* sv_src[R];
@@ -158,7 +166,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, int b, int j,
         const int yrs = left_edge ? (-R + k) : (DW + k);
         sv_y[k] = yL + yrs;
         sv_present[k] = side_wave && needed(yrs, H - 1);
-        sv_src[k] = level_src(sv_y[k], a.t0 + H - 1);
+        sv_src[k] = level_src(sv_y[k], row.t0 + H - 1);
     }
 
     T q[L + 1][Q];

@@ -19,4 +19,12 @@ int tune_choose(int kind, int dtype, int nx, int ny, int nz, TuneChoice* out)
     return STENCIL_OK;
 }
 
+MwdShape tune_batch_shape(int kind, int dtype, int nx, int ny, int nz, int T)
+{
+    (void)dtype; (void)nx; (void)ny; (void)nz; (void)T;
+    if (kind == K25C || kind == K25V) return MwdShape{16, 1};
+    if (kind == K7V) return MwdShape{4, 4};
+    return MwdShape{8, 2};
+}
+
 }  // namespace mwd

@@ -17,4 +17,8 @@ MwdShape default_shape(int kind, int dtype);
 // Returns a STENCIL_* code.
 int tune_choose(int kind, int dtype, int nx, int ny, int nz, TuneChoice* out);
 
+// Tile shape of one grid inside the batched kernel (one of the shapes compiled
+// into it, all sized for 1024-thread workgroups).
+MwdShape tune_batch_shape(int kind, int dtype, int nx, int ny, int nz, int T);
+
 }  // namespace mwd

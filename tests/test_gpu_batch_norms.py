@@ -1,0 +1,83 @@
+"""GPU: the batched persistent form and the FP64 reductions, through the C ABI,
+against the CPU oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import gridgen
+import oracle
+import paper_1410_5561_amd as S
+from gpu_util import device_coeffs, device_grid, run_gpu
+from oracle import norms as onorms
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [("7c", (40, 33, 20)), ("25c", (50, 37, 18)), ("7c", (17, 70, 9)), ("25c", (33, 16, 40)),
+         ("7c", (130, 5, 7)), ("25c", (64, 64, 11)), ("7c", (3, 2, 1)), ("25c", (1, 9, 30)),
+         ("7c", (96, 48, 32))]
+
+
+def _inputs(kind, n, dtype, seed):
+    R = gridgen.RADIUS[kind]
+    u0 = gridgen.field(seed, *n, R, -1.0, 1.0, dtype)
+    co = gridgen.C7 if kind == "7c" else gridgen.C25
+    return u0, co
+
+
+@pytest.mark.parametrize("dts", ["f32", "f64"])
+@pytest.mark.parametrize("T", [16, 5])
+def test_batched_mixed_grids_bitexact_and_replay(dts, T):
+    import torch
+    dtype = np.float64 if dts == "f64" else np.float32
+    print("batched", dts, "T", T, flush=True)
+    inputs = [_inputs(k, n, dtype, 100 + i) for i, (k, n) in enumerate(SPECS)]
+    grids, keep, coeffs = [], [], []
+    for (kind, n), (u0, co) in zip(SPECS, inputs):
+        g, bufs = device_grid(u0, gridgen.RADIUS[kind], 0)
+        c, _ = device_coeffs(kind, co, dtype)
+        grids.append(g)
+        keep.append(bufs)
+        coeffs.append(c)
+    plan = S.Plan("mixed", dts)
+    for rep in (1, 2, 3):
+        plan.run_batched(grids, coeffs, T)
+        torch.cuda.synchronize()
+        for i, ((kind, n), (u0, co)) in enumerate(zip(SPECS, inputs)):
+            got = keep[i][grids[i].cur].cpu().numpy()
+            gotm1 = keep[i][grids[i].cur ^ 1].cpu().numpy()
+            uT, uTm1 = oracle.run(kind, u0, co, rep * T)
+            assert np.array_equal(got, uT), "grid %d (%s %s) after %d runs" % (i, kind, n, rep)
+            assert np.array_equal(gotm1, uTm1), "grid %d u_{T-1}" % i
+    plan.close()
+
+
+@pytest.mark.parametrize("dts", ["f64", "f32"])
+def test_norms_against_oracle(dts):
+    import torch
+    dtype = np.float64 if dts == "f64" else np.float32
+    n, T = (70, 45, 33), 7
+    print("norms", dts, flush=True)
+    u0 = gridgen.field(9, *n, 1, 0.0, 1.0, dtype)
+    C = [c.astype(dtype) for c in gridgen.coeffs_7v(9, *n, 1)]
+    g, bufs = device_grid(u0, 1, 0)
+    c, _ = device_coeffs("7v", C, dtype)
+    plan = S.Plan("7v", dts, *n, mode="mwd", dw=8, lanes=64)
+    plan.run(g, c, T)
+    torch.cuda.synchronize()
+    uT, uTm1 = oracle.run("7v", u0, C, T)
+    l2, mx = S.stencil_norms(g, 0)
+    rl2, rmx = onorms.grid_norms(uT, 1)
+    # sum of n squares in another order: |err| <= n * u * sum (a loose bound);
+    # the tree order here stays far below it
+    assert abs(l2 - rl2) <= 1e-13 * rl2 and mx == rmx
+    rl2, rmx = onorms.residual_norms(uT, uTm1, 1)
+    l2, mx = S.stencil_norms(g, 1)
+    assert abs(l2 - rl2) <= 1e-13 * rl2 and mx == rmx
+    # diff norms between grids of different precision
+    u64 = u0.astype(np.float64)
+    g2, bufs2 = device_grid(u64, 1, 0)
+    d2 = S.stencil_diff_norms(g, g2)
+    rd = onorms.diff_norms(uT, u64, 1, 1)
+    assert abs(d2[0] - rd[0]) <= 1e-13 * rd[0] and d2[1] == rd[1]
+    plan.close()

@@ -1,0 +1,103 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times (plans created without parameters: the autotuned schedule).
+
+The oracle cannot sweep a 512^3 grid 64 times in a test, so it recomputes
+sampled outputs one by one from their dependency cones (tests/cone.py),
+bit for bit; properties that hold at any size (positivity and the maximum
+principle for non-negative weights summing to < 1) are checked on the whole
+result with the library's FP64 norms.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import cone
+import gridgen
+import oracle
+import paper_1410_5561_amd as S
+from oracle import norms as onorms
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_full(windex, dtype):
+    import torch
+    w = gridgen.workloads()[windex]
+    kind, (nx, ny, nz), T = w["kind"], w["n"], w["T"]
+    R = gridgen.RADIUS[kind]
+    seed = gridgen.seed_for_config(windex)
+    npdt = np.float64 if dtype == "f64" else np.float32
+    print("workload", windex, w["name"], dtype, "generating", flush=True)
+    u0 = gridgen.field(seed, nx, ny, nz, R, *w["field"], dtype=npdt)
+    if w["coeffs"] == "7v":
+        co = gridgen.coeffs_7v(seed, nx, ny, nz, R, dtype=npdt)
+        c_dev = [torch.from_numpy(c).cuda() for c in co]
+        coeffs = S.make_coeffs(kind, arrays=c_dev)
+    else:
+        co = list(w["coeffs"])
+        c_dev = []
+        coeffs = S.make_coeffs(kind, consts=co)
+    a = torch.from_numpy(u0).cuda()
+    b = a.clone()
+    g = S.make_grid(a, b, R, 0)
+    plan = S.Plan(kind, dtype, nx, ny, nz)   # autotuned, as the benchmark
+    print("workload", windex, "running", flush=True)
+    plan.run(g, coeffs, T)
+    torch.cuda.synchronize()
+    desc = plan.describe()
+    print("workload", windex, "schedule", desc, flush=True)
+    return w, u0, co, g, (a, b), plan, c_dev
+
+
+def _check_samples(w, u0, co, g, bufs, count):
+    kind, n, T = w["kind"], w["n"], w["T"]
+    R = gridgen.RADIUS[kind]
+    res = bufs[g.cur]
+    for p in cone.sample_points(n, count, seed=T):
+        got = res[p[2] + R, p[1] + R, p[0] + R].item()
+        ref = cone.subbox_value(kind, u0, co, T, R, p)
+        assert got == ref, "point %s: gpu %r oracle %r" % (p, got, ref)
+
+
+@pytest.mark.parametrize("windex,dtype,count", [(2, "f64", 10), (3, "f64", 5), (3, "f32", 5),
+                                                (4, "f32", 5)])
+def test_fullsize_sampled_bitexact(windex, dtype, count):
+    w, u0, co, g, bufs, plan, keep = _run_full(windex, dtype)
+    _check_samples(w, u0, co, g, bufs, count)
+    l2, mx = S.stencil_norms(g, 0)
+    u0max = float(np.max(np.abs(u0)))
+    assert np.isfinite(l2) and mx <= u0max   # weights are non-negative with sum < 1
+    plan.close()
+
+
+def test_f32_error_subrun_against_f64_oracle():
+    """The FP32 precision form on the 256^3 sub-run of the 7-point variable
+    workload (T = 100): max-norm error against the FP64 oracle on the same
+    FP32-rounded inputs, within the bound T (m + 1) u32 ||u_0|| (m = 13)."""
+    import torch
+    n, T = (256, 256, 256), 100
+    seed = gridgen.seed_for_config(4)
+    u0 = gridgen.field(seed, *n, 1, 0.0, 1.0, dtype=np.float32)
+    C = gridgen.coeffs_7v(seed, *n, 1, dtype=np.float32)
+    print("f32 sub-run 256^3 T=100", flush=True)
+    a = torch.from_numpy(u0).cuda()
+    b = a.clone()
+    g = S.make_grid(a, b, 1, 0)
+    cdev = [torch.from_numpy(c).cuda() for c in C]
+    plan = S.Plan("7v", "f32", *n)
+    plan.run(g, S.make_coeffs("7v", arrays=cdev), T)
+    torch.cuda.synchronize()
+    got = (a, b)[g.cur].cpu().numpy().astype(np.float64)
+    ref, refm1 = oracle.run("7v", u0.astype(np.float64), [c.astype(np.float64) for c in C], T)
+    err = float(np.max(np.abs(got - ref)))
+    bound = T * 14 * 2.0 ** -24 * float(np.max(u0))
+    print("f32 max-norm error %.3e (relative %.3e), bound %.3e" % (err, err / np.max(np.abs(ref)), bound),
+          flush=True)
+    assert err <= bound
+    # the GPU's FP64 residual norms of the FP32 run against the oracle's FP32 run
+    r32, r32m1 = oracle.run("7v", u0, C, T)
+    l2, mx = S.stencil_norms(g, 1)
+    rl2, rmx = onorms.residual_norms(r32, r32m1, 1)
+    assert abs(l2 - rl2) <= 1e-12 * rl2 and mx == rmx
+    plan.close()
