@@ -118,7 +118,8 @@ int stencil_create(stencil_plan **out, int32_t kind, int32_t dtype,
 
 /* Advance `grid` by T time steps (Sec. I, Listings 1-3) on `stream`
  * (asynchronous).  T == 0 is a no-op.  MWD plans allocate device scratch
- * (two more grid-sized arrays) on first use and keep it until destroy; the
+ * (four more grid-sized arrays: two buffer pairs) on first use and keep it
+ * until destroy; the
  * scratch holds intermediate levels so that concurrently running x-tiles
  * never read a value another tile overwrites.  Errors: EINVAL (null
  * pointers, size or dtype mismatch with the plan, halo < R, T < 0, bad
@@ -129,16 +130,21 @@ int stencil_run(stencil_plan *plan, stencil_grid *grid, const stencil_coeffs *co
 /* Release a plan: waits for its work, frees its scratch and graphs. */
 int stencil_destroy(stencil_plan *plan);
 
-/* Advance n independent grids (uneven sizes, kinds 7c/25c/7v/25v, one dtype)
- * by T steps in ONE persistent kernel launch captured in a hipGraph.  Tiles
- * of all grids form one dependency graph; workgroups take tiles from a device
- * counter in a topological order and wait on per-tile dependency counters.
- * Diamond width and x lanes are chosen per (kind, size) bucket.  The first
- * call for a given set of grids builds the tile table and captures the graph;
- * later calls with the same grids (same pointers, sizes and cur) replay it.
- * On return every grids[i].cur is updated as by stencil_run.  The plan must
- * have been created with STENCIL_KIND_MIXED or the grids' common kind.
- * Errors: as stencil_run; EDEVICE also if a dependency wait timed out. */
+/* Advance n independent grids (uneven sizes, kinds 7c/25c in both dtypes,
+ * 7v in FP32; one dtype per call) by T steps with ONE hipGraph launch.  The
+ * MWD tiles of all grids are grouped by diamond row; each group is one kernel
+ * launch (a workgroup per tile, any grid), and the group launches plus a
+ * final gather are captured into a graph once and replayed (kernel
+ * boundaries are the row-to-row dependencies; no workgroup waits on
+ * another).  Diamond width and x lanes are autotuned per (kind, size bucket)
+ * among the shapes compiled into the batched kernel.  The first call for a
+ * given set of grids builds the tile table, allocates scratch (two extra
+ * buffer pairs per grid) and captures the graph; later calls with the same
+ * grids (same pointers, sizes, weights and cur) replay it; two such sets are
+ * cached.  Asynchronous on `stream`; on return every grids[i].cur is updated
+ * as by stencil_run.  The plan must have been created with
+ * STENCIL_KIND_MIXED or the grids' common kind.  Errors: as stencil_run;
+ * EUNSUPPORTED for a kind/dtype without a batched tile shape. */
 int stencil_run_batched(stencil_plan *plan, stencil_grid *grids, const stencil_coeffs *coeffs,
                         int32_t n, int32_t T, void *stream);
 

@@ -269,7 +269,7 @@ int stencil_run(stencil_plan* p, stencil_grid* g, const stencil_coeffs* c, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!p->chosen) {
         TuneChoice tc;
-        rc = tune_choose(p->kind, p->dtype, p->nx, p->ny, p->nz, &tc);
+        rc = tune_choose(p->kind, p->dtype, p->nx, p->ny, p->nz, T, &tc);
         if (rc) return rc;
         p->mode = tc.mode;
         p->shape = tc.shape;

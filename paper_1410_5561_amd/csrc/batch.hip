@@ -16,27 +16,6 @@ int check_grid(const stencil_grid* g, const char* name);
 DevGrid to_dev(const stencil_grid* g);
 int check_coeffs(const stencil_coeffs* c, int kind, const stencil_grid* g, HostWeights* out);
 
-__global__ void batch_reset_kernel(int* done, int ngrids, int* counter, int* err)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ngrids) done[i] = 0;
-    if (i == 0) {
-        *counter = 0;
-        *err = 0;
-    }
-}
-
-hipError_t batch_reset(int* done, int ngrids, int* counter, int* err, hipStream_t s)
-{
-    const int n = ngrids > 0 ? ngrids : 1;
-    hipLaunchKernelGGL(batch_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, done, ngrids, counter, err);
-    return hipGetLastError();
-}
-
-int batch_blocks_per_cu_f64();
-int batch_blocks_per_cu_f32();
-int batch_blocks_per_cu(int dtype) { return dtype == 0 ? batch_blocks_per_cu_f64() : batch_blocks_per_cu_f32(); }
-
 struct BatchKey {
     std::vector<uintptr_t> ptrs;
     std::vector<long long> dims;
@@ -50,9 +29,8 @@ struct BatchGraph {
     BatchKey key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void* dev = nullptr;        // tiles | gargs | gvariant | done | counter | err
+    void* dev = nullptr;        // tiles | gargs | gvariant
     void* scratch = nullptr;    // two extra buffer pairs per grid
-    int* err = nullptr;
     int ntiles = 0;
     std::vector<int> variants;  // chosen variant per grid (for reporting)
     void release() {
@@ -136,7 +114,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     // 3. tile table, rows of all grids interleaved row by row (topological)
     std::vector<MwdArgs<T>> gargs(n);
     std::vector<BatchTile> tiles;
-    std::vector<int> rows(n), nxt(n), nrow_tiles_done(n, 0);
+    std::vector<int> rows(n), nxt(n);
     int max_rows = 0;
     for (int i = 0; i < n; ++i) {
         const BatchVariantInfo& vi = kBatchVariantInfo[var[i]];
@@ -154,45 +132,43 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         nxt[i] = (d.nx + XT - 1) / XT;
         gargs[i].nxt = nxt[i];
         rows[i] = (T_steps + H - 1) / H + 1;  // rows 0 .. rho_max
-        max_rows = std::max(max_rows, rows[i] + 1);  // + the gather "row"
+        max_rows = std::max(max_rows, rows[i]);
     }
+    std::vector<int> group_first;  // table index where each row group starts
     for (int rho = 0; rho < max_rows; ++rho) {
-        // larger grids first within a row: better tail balance
+        group_first.push_back((int)tiles.size());
+        // larger grids first within a group
         std::vector<int> order;
         for (int i = 0; i < n; ++i)
-            if (rho <= rows[i]) order.push_back(i);
+            if (rho < rows[i]) order.push_back(i);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             return (long long)grids[a].nx * grids[a].ny * grids[a].nz > (long long)grids[b].nx * grids[b].ny * grids[b].nz;
         });
         for (int i : order) {
             const BatchVariantInfo& vi = kBatchVariantInfo[var[i]];
             const int R = radius_of(vi.kind), H = vi.dw / (2 * R);
-            if (rho < rows[i]) {
-                const int yoff = (rho % 2) * (vi.dw / 2);
-                const int ybase = yoff > 0 ? yoff - vi.dw : 0;
-                const int nB = (grids[i].ny - 1 - ybase) / vi.dw + 1;
-                const int need = nrow_tiles_done[i];
-                for (int b = 0; b < nB; ++b)
-                    for (int j = 0; j < nxt[i]; ++j)
-                        tiles.push_back(BatchTile{i, var[i], rho, (rho - 1) * H, ybase, b, j, need});
-                nrow_tiles_done[i] += nB * nxt[i];
-            } else {
-                // gather after the last row, in chunks of planes
-                const int need = nrow_tiles_done[i];
-                const int zc = std::max(1, (int)(65536 / std::max(1LL, (long long)grids[i].nx * grids[i].ny)));
-                for (int z0 = 0; z0 < grids[i].nz; z0 += zc)
-                    tiles.push_back(BatchTile{i, kGatherVariant, -1, 0, 0, z0, std::min(zc, grids[i].nz - z0), need});
-            }
+            const int yoff = (rho % 2) * (vi.dw / 2);
+            const int ybase = yoff > 0 ? yoff - vi.dw : 0;
+            const int nB = (grids[i].ny - 1 - ybase) / vi.dw + 1;
+            for (int b = 0; b < nB; ++b)
+                for (int j = 0; j < nxt[i]; ++j)
+                    tiles.push_back(BatchTile{i, 0, rho, (rho - 1) * H, ybase, b, j, 0});
         }
     }
+    // the gather of every grid's last two levels
+    group_first.push_back((int)tiles.size());
+    for (int i = 0; i < n; ++i) {
+        const int zc = std::max(1, (int)(65536 / std::max(1LL, (long long)grids[i].nx * grids[i].ny)));
+        for (int z0 = 0; z0 < grids[i].nz; z0 += zc)
+            tiles.push_back(BatchTile{i, 1, -1, 0, 0, z0, std::min(zc, grids[i].nz - z0), 0});
+    }
+    group_first.push_back((int)tiles.size());
     // 4. device tables
     const size_t tb = tiles.size() * sizeof(BatchTile);
     const size_t ab = (size_t)n * sizeof(MwdArgs<T>);
     const size_t vb = (size_t)n * sizeof(int);
-    const size_t db = (size_t)n * sizeof(int);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t total = al(tb) + al(ab) + al(vb) + al(db) + 256 + 256;
-    if (hipMalloc(&bg.dev, total) != hipSuccess) {
+    if (hipMalloc(&bg.dev, al(tb) + al(ab) + al(vb)) != hipSuccess) {
         (void)hipGetLastError();
         bg.dev = nullptr;
         *errmsg = "batched table allocation failed";
@@ -202,9 +178,6 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     BatchTile* d_tiles = reinterpret_cast<BatchTile*>(base);
     MwdArgs<T>* d_args = reinterpret_cast<MwdArgs<T>*>(base + al(tb));
     int* d_var = reinterpret_cast<int*>(base + al(tb) + al(ab));
-    int* d_done = reinterpret_cast<int*>(base + al(tb) + al(ab) + al(vb));
-    int* d_counter = reinterpret_cast<int*>(base + al(tb) + al(ab) + al(vb) + al(db));
-    int* d_err = reinterpret_cast<int*>(base + al(tb) + al(ab) + al(vb) + al(db) + 256);
     hipError_t e = hipMemcpy(d_tiles, tiles.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_args, gargs.data(), ab, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_var, var.data(), vb, hipMemcpyHostToDevice);
@@ -212,19 +185,9 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         *errmsg = std::string("batched table upload: ") + hipGetErrorString(e);
         return STENCIL_EDEVICE;
     }
-    bg.err = d_err;
     bg.ntiles = (int)tiles.size();
     bg.variants = var;
-    // 5. capture: reset counters, then the persistent kernel
-    int dev = 0, ncu = 0, wall_khz = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev);
-    if (ncu <= 0) ncu = 256;
-    if (wall_khz <= 0) wall_khz = 100000;
-    const int nblocks = std::max(1, std::min(bg.ntiles, ncu * batch_blocks_per_cu(dtype)));
-    BatchLaunch<T> L{d_tiles, bg.ntiles, d_args, d_var, d_done, d_counter, d_err,
-                     (long long)wall_khz * 1000LL * 4};  // a dependency wait gives up after 4 s
+    // 5. capture one launch per group, in order, into a graph
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -233,13 +196,16 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = batch_reset(d_done, n, d_counter, d_err, cs);
-        hipError_t e2;
-        if constexpr (sizeof(T) == 8) e2 = batch_launch_f64(L, nblocks, cs);
-        else e2 = batch_launch_f32(L, nblocks, cs);
+        hipError_t el = hipSuccess;
+        for (size_t g = 0; g + 1 < group_first.size() && el == hipSuccess; ++g) {
+            const int cnt = group_first[g + 1] - group_first[g];
+            if (cnt <= 0) continue;
+            BatchLaunch<T> L{d_tiles, group_first[g], d_args, d_var};
+            if constexpr (sizeof(T) == 8) el = batch_launch_f64(L, cnt, cs);
+            else el = batch_launch_f32(L, cnt, cs);
+        }
         e = hipStreamEndCapture(cs, &bg.graph);
-        if (e == hipSuccess && e1 != hipSuccess) e = e1;
-        if (e == hipSuccess && e2 != hipSuccess) e = e2;
+        if (e == hipSuccess && el != hipSuccess) e = el;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0);
     (void)hipStreamDestroy(cs);
@@ -324,19 +290,6 @@ int batch_run(int plan_kind, int plan_dtype, BatchState** state, stencil_grid* g
     hipError_t e = hipGraphLaunch(bg->exec, stream);
     if (e != hipSuccess) {
         set_last_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e));
-        return STENCIL_EDEVICE;
-    }
-    // the launch is synchronous towards the caller: wait, then check that no
-    // dependency wait gave up
-    int herr = 0;
-    e = hipMemcpyAsync(&herr, bg->err, sizeof(int), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) {
-        set_last_error(std::string("batched run: ") + hipGetErrorString(e));
-        return STENCIL_EDEVICE;
-    }
-    if (herr) {
-        set_last_error("a batched tile's dependency wait timed out");
         return STENCIL_EDEVICE;
     }
     for (int i = 0; i < n; ++i) grids[i].cur ^= (T & 1);

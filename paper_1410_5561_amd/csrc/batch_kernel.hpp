@@ -1,22 +1,14 @@
-// Persistent kernel of the batched form: many independent grids advanced in
-// one launch.  The tiles of every grid (MWD diamond x x-tile tiles, one row
-// after another, then the gather of the grid's last two levels) form one
-// table in a topological order; each workgroup repeatedly takes the next
-// ticket from a device counter, waits until the tiles its tile depends on are
-// complete, runs it, and publishes its completion.
+// Kernels of the batched form: many independent grids advanced together.
 //
-// Dependencies are per grid and per row: a tile of row rho starts once every
-// tile of rows < rho of the same grid has completed (the `need` count of the
-// grid's completion counter).  That covers the reads (rows rho-1, rho-2) and
-// the reuse of buffer pair (rho+1) mod 3, last read by rows rho-1 and rho-2.
-// Because every tile only waits on tiles with smaller tickets, and a ticket is
-// only taken by a running workgroup, the smallest unfinished ticket can
-// always proceed: the schedule cannot deadlock.  Completion is published with
-// an agent-scope release after the tile's stores and observed with an
-// agent-scope acquire before the dependent tile's loads (the workgroups may
-// sit on different XCDs, whose L2 caches are not coherent with each other).
-// A wait that exceeds a wall-clock limit sets an error flag and gives up, so
-// the kernel always drains.
+// The tiles of all grids are laid out in one table, grouped by diamond row:
+// group rho holds the row-rho tiles (diamond x x-tile) of every grid that has
+// such a row; a final group holds the gather of each grid's last two levels
+// out of the rotating buffer pairs.  Group rho runs as one kernel launch in
+// which every workgroup computes one tile; the launches of all groups are
+// captured once into a hipGraph and replayed with a single hipGraphLaunch.
+// Kernel boundaries carry the dependencies (row rho reads what rows rho-1 and
+// rho-2 wrote, and reuses the pair rows rho-3 wrote, already consumed), so no
+// workgroup ever waits on another one.
 #pragma once
 
 #include "mwd_tile.hpp"
@@ -25,13 +17,12 @@ namespace mwd {
 
 struct BatchTile {
     int grid;     // index into the per-grid argument table
-    int variant;  // tile shape (index into the batch variant list), or kGatherVariant
+    int gather;   // 0: an MWD tile; 1: a gather tile
     int rho, t0, ybase;
     int b, j;     // diamond and x tile; for gather tiles: first plane and plane count
-    int need;     // completed tiles of this grid required before starting
+    int pad;
 };
 
-constexpr int kGatherVariant = 255;
 constexpr int kBatchThreads = 1024;
 
 // Copy u_T and u_{T-1} of planes [z0, z0 + nzc) out of the rotating pairs into
@@ -86,7 +77,7 @@ __device__ __forceinline__ void batch_dispatch(int variant, const MwdArgs<T>& a,
     if (variant == I) {
         using G = MwdGeom<V::kind, V::dw, V::wpr>;
         static_assert(G::NT <= kBatchThreads, "tile shape larger than the batch workgroup");
-        if (t.variant == kGatherVariant) {
+        if (t.gather) {
             batch_gather<T, G::R, V::dw>(a, t.b, t.j);
         } else {
             mwd_tile<V::kind, T, V::dw, V::wpr>(
@@ -97,45 +88,15 @@ __device__ __forceinline__ void batch_dispatch(int variant, const MwdArgs<T>& a,
     if constexpr (sizeof...(Rest) > 0) batch_dispatch<T, I + 1, Rest...>(variant, a, row, t, lds);
 }
 
+// Workgroup blockIdx.x computes tile first + blockIdx.x of the table.
 template <typename T, class... V>
-__device__ __forceinline__ void batch_loop(const BatchTile* __restrict__ tiles, int ntiles,
-                                           const MwdArgs<T>* __restrict__ gargs,
-                                           const int* __restrict__ gvariant,
-                                           int* done, int* counter, int* err, long long spin_limit,
-                                           char* lds)
+__device__ __forceinline__ void batch_group(const BatchTile* __restrict__ tiles, int first,
+                                            const MwdArgs<T>* __restrict__ gargs,
+                                            const int* __restrict__ gvariant, char* lds)
 {
-    __shared__ int s_ticket;
-    for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(counter, 1);
-        __syncthreads();
-        const int tk = s_ticket;
-        __syncthreads();
-        if (tk >= ntiles) break;
-        const BatchTile t = tiles[tk];
-        if (threadIdx.x == 0) {
-            if (t.need > 0) {
-                const long long start = wall_clock64();
-                while (__hip_atomic_load(&done[t.grid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < t.need) {
-                    __builtin_amdgcn_s_sleep(4);
-                    if (wall_clock64() - start > spin_limit) {
-                        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                }
-            }
-            // acquire: later loads of this workgroup see the producers' stores
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
-        const MwdRow row{t.rho, t.t0, t.ybase};
-        batch_dispatch<T, 0, V...>(gvariant[t.grid], gargs[t.grid], row, t, lds);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            // release: this tile's stores are visible before the count moves
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(&done[t.grid], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    const BatchTile t = tiles[first + blockIdx.x];
+    const MwdRow row{t.rho, t.t0, t.ybase};
+    batch_dispatch<T, 0, V...>(gvariant[t.grid], gargs[t.grid], row, t, lds);
 }
 
 }  // namespace mwd

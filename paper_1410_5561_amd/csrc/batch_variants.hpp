@@ -27,18 +27,12 @@ constexpr int kNumBatchVariantsF64 = 4;
 template <typename T>
 struct BatchLaunch {
     const BatchTile* tiles;
-    int ntiles;
+    int first;            // first table entry of this group
     const MwdArgs<T>* gargs;
     const int* gvariant;
-    int* done;
-    int* counter;
-    int* err;
-    long long spin_limit;
 };
 
 hipError_t batch_launch_f64(const BatchLaunch<double>& L, int nblocks, hipStream_t s);
 hipError_t batch_launch_f32(const BatchLaunch<float>& L, int nblocks, hipStream_t s);
-hipError_t batch_reset(int* done, int ngrids, int* counter, int* err, hipStream_t s);
-int batch_blocks_per_cu(int dtype);
 
 }  // namespace mwd

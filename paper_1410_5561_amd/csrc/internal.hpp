@@ -91,6 +91,10 @@ struct MwdShape {
 // True if a compiled MWD kernel exists for (kind, dtype, shape).
 bool mwd_supported(int kind, int dtype, const MwdShape& s);
 int mwd_levels(int kind, const MwdShape& s);
+// All compiled shapes for (kind, dtype); returns how many were written.
+int mwd_shapes(int kind, int dtype, MwdShape* out, int cap);
+// Whether the shape's row kernel keeps values in scratch memory (register spill).
+hipError_t mwd_kernel_spills(int kind, int dtype, const MwdShape& s, bool* spills);
 int mwd_xtile(int kind, const MwdShape& s);
 
 // Run T steps with MWD.  `scratch` holds two extra grid-sized buffer pairs

@@ -34,6 +34,31 @@ static const MwdEntry* find_entry(int kind, int dtype, const MwdShape& s)
 
 bool mwd_supported(int kind, int dtype, const MwdShape& s) { return find_entry(kind, dtype, s) != nullptr; }
 
+int mwd_shapes(int kind, int dtype, MwdShape* out, int cap)
+{
+    if (kind < 0 || kind > 3 || dtype < 0 || dtype > 1) return 0;
+    static const int dws[] = {4, 8, 16};
+    static const int wprs[] = {1, 2, 4};
+    int n = 0;
+    for (int dw : dws)
+        for (int wpr : wprs) {
+            MwdShape s{dw, wpr};
+            if (find_entry(kind, dtype, s) && n < cap) out[n++] = s;
+        }
+    return n;
+}
+
+hipError_t mwd_kernel_spills(int kind, int dtype, const MwdShape& s, bool* spills)
+{
+    const MwdEntry* e = find_entry(kind, dtype, s);
+    if (!e) return hipErrorInvalidValue;
+    hipFuncAttributes fa;
+    hipError_t err = hipFuncGetAttributes(&fa, e->kernel);
+    if (err != hipSuccess) return err;
+    *spills = fa.localSizeBytes > 0;
+    return hipSuccess;
+}
+
 int mwd_levels(int kind, const MwdShape& s) { return s.dw / radius_of(kind) - 1; }
 
 int mwd_xtile(int kind, const MwdShape& s) { return 64 * s.wpr - 2 * mwd_levels(kind, s) * radius_of(kind); }

@@ -4,7 +4,7 @@
 namespace mwd {
 
 static const MwdEntry kEntries[] = {
-    MWD_ENTRY(K25C, float, 1, 8, 1), MWD_ENTRY(K25C, float, 1, 16, 1),
+    MWD_ENTRY(K25C, float, 1, 8, 1), MWD_ENTRY(K25C, float, 1, 16, 1), MWD_ENTRY(K25C, float, 1, 8, 2),
 };
 
 void mwd_table_25c_f32(const MwdEntry** tab, int* n)

@@ -4,7 +4,7 @@
 namespace mwd {
 
 static const MwdEntry kEntries[] = {
-    MWD_ENTRY(K25V, double, 0, 8, 1), MWD_ENTRY(K25V, double, 0, 16, 1),
+    MWD_ENTRY(K25V, double, 0, 8, 1), MWD_ENTRY(K25V, double, 0, 16, 1), MWD_ENTRY(K25V, double, 0, 8, 2),
 };
 
 void mwd_table_25v_f64(const MwdEntry** tab, int* n)

@@ -5,7 +5,7 @@ namespace mwd {
 
 static const MwdEntry kEntries[] = {
     MWD_ENTRY(K7C, float, 1, 4, 1), MWD_ENTRY(K7C, float, 1, 4, 2), MWD_ENTRY(K7C, float, 1, 8, 1),
-    MWD_ENTRY(K7C, float, 1, 8, 2), MWD_ENTRY(K7C, float, 1, 16, 1),
+    MWD_ENTRY(K7C, float, 1, 8, 2), MWD_ENTRY(K7C, float, 1, 16, 1), MWD_ENTRY(K7C, float, 1, 4, 4),
 };
 
 void mwd_table_7c_f32(const MwdEntry** tab, int* n)

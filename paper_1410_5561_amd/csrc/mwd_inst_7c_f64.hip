@@ -5,7 +5,7 @@ namespace mwd {
 
 static const MwdEntry kEntries[] = {
     MWD_ENTRY(K7C, double, 0, 4, 1), MWD_ENTRY(K7C, double, 0, 4, 2), MWD_ENTRY(K7C, double, 0, 8, 1),
-    MWD_ENTRY(K7C, double, 0, 8, 2),
+    MWD_ENTRY(K7C, double, 0, 8, 2), MWD_ENTRY(K7C, double, 0, 4, 4),
 };
 
 void mwd_table_7c_f64(const MwdEntry** tab, int* n)

@@ -5,7 +5,7 @@ namespace mwd {
 
 static const MwdEntry kEntries[] = {
     MWD_ENTRY(K7V, double, 0, 4, 1), MWD_ENTRY(K7V, double, 0, 4, 2), MWD_ENTRY(K7V, double, 0, 8, 1),
-    MWD_ENTRY(K7V, double, 0, 8, 2),
+    MWD_ENTRY(K7V, double, 0, 8, 2), MWD_ENTRY(K7V, double, 0, 4, 4),
 };
 
 void mwd_table_7v_f64(const MwdEntry** tab, int* n)

@@ -96,11 +96,13 @@ struct MwdEntry {
     int kind, dtype, dw, wpr;
     RunFn fn;
     int levels, xtile;
+    const void* kernel;  // the row kernel, for resource queries
 };
 
 #define MWD_ENTRY(K, TT, DTI, DW, WPR)                                               \
     MwdEntry{K, DTI, DW, WPR, &run_rows<K, TT, DW, WPR>, MwdGeom<K, DW, WPR>::L,     \
-             MwdGeom<K, DW, WPR>::XT}
+             MwdGeom<K, DW, WPR>::XT,                                                \
+             reinterpret_cast<const void*>(&mwd_row_kernel<K, TT, DW, WPR>)}
 
 
 }  // namespace mwd

@@ -1,6 +1,25 @@
+// Autotuner: choose between the naive sweep and the compiled MWD shapes
+// (diamond width, x lanes) by timing them on a proxy grid of the same x-y
+// extent, in the spirit of the paper's auto-tuning of diamond width, frontlines
+// and x-tile (Sec. II-A, Sec. IV-B).  The search space is pruned to shapes
+// whose tile kernel holds its working set in registers and LDS (a shape that
+// spills to scratch memory is not tried), the analogue of keeping the cache
+// block inside the cache (Sec. III-B).  Choices are cached per device and
+// size bucket for the life of the process and, if MWD_TUNE_CACHE names a
+// file, across processes.
 #include "tune.hpp"
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
 #include "../../include/mwd_stencil.h"
+#include "batch_variants.hpp"
 
 namespace mwd {
 
@@ -11,17 +30,231 @@ MwdShape default_shape(int kind, int dtype)
     return MwdShape{8, 2};
 }
 
-int tune_choose(int kind, int dtype, int nx, int ny, int nz, TuneChoice* out)
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int, int, int>;  // dev kind dtype nx ny nzp Tp batch
+
+std::mutex g_mu;
+std::map<Key, TuneChoice> g_cache;
+bool g_file_loaded = false;
+
+constexpr int kProxyNz = 48;
+constexpr int kProxyT = 16;
+
+const char* cache_path()
 {
-    (void)nx; (void)ny; (void)nz;
-    out->mode = STENCIL_MODE_MWD;
-    out->shape = default_shape(kind, dtype);
+    const char* p = std::getenv("MWD_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+void load_file()
+{
+    if (g_file_loaded) return;
+    g_file_loaded = true;
+    const char* path = cache_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    int v[11];
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                       &v[7], &v[8], &v[9], &v[10]) == 11) {
+        g_cache[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]}] = TuneChoice{v[8], MwdShape{v[9], v[10]}};
+    }
+    std::fclose(f);
+}
+
+void save_entry(const Key& k, const TuneChoice& c)
+{
+    const char* path = cache_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k), c.mode,
+                 c.shape.dw, c.shape.wpr);
+    std::fclose(f);
+}
+
+// MWD_TUNE=naive or MWD_TUNE=mwd:<dw>:<lanes> forces a choice (measurement sweeps).
+bool forced(int kind, int dtype, TuneChoice* out)
+{
+    const char* e = std::getenv("MWD_TUNE");
+    if (!e || !*e) return false;
+    if (std::strcmp(e, "naive") == 0) {
+        *out = TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}};
+        return true;
+    }
+    int dw = 0, lanes = 0;
+    if (std::sscanf(e, "mwd:%d:%d", &dw, &lanes) == 2 && lanes % 64 == 0) {
+        MwdShape s{dw, lanes / 64};
+        if (mwd_supported(kind, dtype, s)) {
+            *out = TuneChoice{STENCIL_MODE_MWD, s};
+            return true;
+        }
+    }
+    return false;
+}
+
+struct Proxy {
+    std::vector<void*> allocs;
+    DevGrid g{};
+    HostWeights w{};
+    void* scratch[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~Proxy() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    bool alloc(size_t bytes, void** base) {
+        if (hipMalloc(base, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        allocs.push_back(*base);
+        return hipMemset(*base, 0, bytes) == hipSuccess;
+    }
+};
+
+bool make_proxy(Proxy& P, int kind, int dtype, int nx, int ny, int nz)
+{
+    const int h = radius_of(kind);
+    const size_t es = dtype == 0 ? 8 : 4;
+    P.g.nx = nx;
+    P.g.ny = ny;
+    P.g.nz = nz;
+    P.g.halo = h;
+    P.g.sy = nx + 2 * h;
+    P.g.sz = P.g.sy * (ny + 2 * h);
+    P.g.dtype = dtype;
+    P.g.cur = 0;
+    const size_t bytes = (size_t)P.g.sz * (nz + 2 * h) * es;
+    const long long off = (long long)h * P.g.sz + (long long)h * P.g.sy + h;
+    void* base = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (!P.alloc(bytes, &base)) return false;
+        P.g.org[i] = static_cast<char*>(base) + off * es;
+    }
+    for (int i = 0; i < 4; ++i) {
+        if (!P.alloc(bytes, &base)) return false;
+        P.scratch[i] = static_cast<char*>(base) + off * es;
+    }
+    P.w.kind = kind;
+    for (int m = 0; m < 13; ++m) {
+        P.w.c[m] = 0.05;
+        P.w.org[m] = nullptr;
+    }
+    for (int m = 0; m < narr_of(kind); ++m) {
+        if (!P.alloc(bytes, &base)) return false;
+        P.w.org[m] = static_cast<char*>(base) + off * es;
+    }
+    return true;
+}
+
+// Milliseconds per run of T steps with the given choice, or a negative value.
+double time_choice(Proxy& P, int T, const TuneChoice& c, hipStream_t s)
+{
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1.0;
+    }
+    auto run = [&]() -> hipError_t {
+        if (c.mode == STENCIL_MODE_NAIVE) {
+            for (int t = 0; t < T; ++t) {
+                hipError_t e = naive_sweep(P.g, P.w, P.g.org[t & 1], P.g.org[(t + 1) & 1], s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }
+        return mwd_run(P.g, P.w, T, c.shape, P.scratch, s, nullptr);
+    };
+    double ms = -1.0;
+    hipError_t e = run();  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float f = 0.f;
+    if (e == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = f / 3.0;
+    (void)hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
+}
+
+int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch, TuneChoice* out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return STENCIL_EDEVICE;
+    const int nzp = nz < kProxyNz ? nz : kProxyNz;
+    const int Tp = T < kProxyT ? (T > 0 ? T : 1) : kProxyT;
+    const Key key{dev, kind, dtype, nx, ny, nzp, Tp, batch ? 1 : 0};
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file();
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        *out = it->second;
+        return STENCIL_OK;
+    }
+    // candidates
+    std::vector<TuneChoice> cands;
+    if (batch) {
+        const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
+        for (int i = 0; i < nv; ++i)
+            if (kBatchVariantInfo[i].kind == kind)
+                cands.push_back(TuneChoice{STENCIL_MODE_MWD, MwdShape{kBatchVariantInfo[i].dw, kBatchVariantInfo[i].wpr}});
+    } else {
+        cands.push_back(TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}});
+        MwdShape shapes[16];
+        const int ns = mwd_shapes(kind, dtype, shapes, 16);
+        for (int i = 0; i < ns; ++i) {
+            bool spills = false;
+            if (mwd_kernel_spills(kind, dtype, shapes[i], &spills) == hipSuccess && !spills)
+                cands.push_back(TuneChoice{STENCIL_MODE_MWD, shapes[i]});
+        }
+    }
+    if (cands.empty()) return STENCIL_EUNSUPPORTED;
+    TuneChoice best = cands[0];
+    if (cands.size() > 1) {
+        Proxy P;
+        hipStream_t s = nullptr;
+        double best_ms = -1.0;
+        if (make_proxy(P, kind, dtype, nx, ny, nzp) && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess) {
+            for (const TuneChoice& c : cands) {
+                // a batched shape is timed through the row kernel of the same tile
+                if (c.mode == STENCIL_MODE_MWD && !mwd_supported(kind, dtype, c.shape)) continue;
+                const double ms = time_choice(P, Tp, c, s);
+                if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+            (void)hipStreamDestroy(s);
+        }
+        (void)hipGetLastError();
+    }
+    g_cache[key] = best;
+    save_entry(key, best);
+    *out = best;
     return STENCIL_OK;
+}
+
+}  // namespace
+
+int tune_choose(int kind, int dtype, int nx, int ny, int nz, int T, TuneChoice* out)
+{
+    if (forced(kind, dtype, out)) return STENCIL_OK;
+    return tune_generic(kind, dtype, nx, ny, nz, T, false, out);
 }
 
 MwdShape tune_batch_shape(int kind, int dtype, int nx, int ny, int nz, int T)
 {
-    (void)dtype; (void)nx; (void)ny; (void)nz; (void)T;
+    // bucket the extents so that a batch of many uneven grids tunes a few
+    // representative sizes
+    auto bucket = [](int n) { return n <= 64 ? 64 : n <= 128 ? 128 : 256; };
+    TuneChoice c;
+    if (tune_generic(kind, dtype, bucket(nx), bucket(ny), bucket(nz), T, true, &c) == STENCIL_OK &&
+        c.mode == STENCIL_MODE_MWD)
+        return c.shape;
     if (kind == K25C || kind == K25V) return MwdShape{16, 1};
     if (kind == K7V) return MwdShape{4, 4};
     return MwdShape{8, 2};

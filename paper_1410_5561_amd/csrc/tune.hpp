@@ -15,7 +15,7 @@ MwdShape default_shape(int kind, int dtype);
 
 // Choose naive or MWD and the MWD shape for grids of this kind, dtype and size.
 // Returns a STENCIL_* code.
-int tune_choose(int kind, int dtype, int nx, int ny, int nz, TuneChoice* out);
+int tune_choose(int kind, int dtype, int nx, int ny, int nz, int T, TuneChoice* out);
 
 // Tile shape of one grid inside the batched kernel (one of the shapes compiled
 // into it, all sized for 1024-thread workgroups).
