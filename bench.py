@@ -247,8 +247,8 @@ def main():
                         "achieved_GBs_at_model_bytes": round(nval * nb, 1)}
         out["speedup_vs_naive"] = round(value / nval, 3)
     if a.sweep:
-        shapes = {1: [(4, 64), (4, 128), (8, 64), (8, 128), (16, 64)],
-                  4: [(8, 64), (16, 64)]}[R]
+        shapes = {1: [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
+                  4: [(8, 64), (8, 128), (16, 64)]}[R]
         sw = []
         for dw, lx in shapes:
             try:

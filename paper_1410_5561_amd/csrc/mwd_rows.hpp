@@ -13,7 +13,7 @@ __global__ void __launch_bounds__(64 * DW * WPR)
 mwd_row_kernel(MwdArgs<T> a, MwdRow row)
 {
     using G = MwdGeom<K, DW, WPR>;
-    __shared__ T ex[2][G::L][G::NS][G::LX];
+    __shared__ T ex[2][G::L][G::NSX][G::LX];
     const int b = blockIdx.x / a.nxt;
     const int j = blockIdx.x % a.nxt;
     mwd_tile<K, T, DW, WPR>(a, row, b, j, ex);
@@ -70,6 +70,24 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
     a.nsteps = nsteps;
     a.nxt = (g.nx + G::XT - 1) / G::XT;
     const int rho_max = (nsteps + G::H - 1) / G::H;
+    // boundary values into the scratch pairs
+    {
+        HaloFill<T> hf;
+        hf.src = a.halo;
+        for (int k = 0; k < 4; ++k) hf.dst[k] = static_cast<T*>(scratch[k]);
+        hf.nx = g.nx;
+        hf.ny = g.ny;
+        hf.nz = g.nz;
+        hf.r = G::R;
+        hf.sy = g.sy;
+        hf.sz = g.sz;
+        dim3 hg((g.nx + 2 * G::R + 63) / 64, (g.ny + 2 * G::R + 3) / 4, 1);
+        if (prof) prof->begin(stream);
+        hipLaunchKernelGGL((mwd_halo_fill_kernel<T>), hg, dim3(256), 0, stream, hf);
+        if (prof) prof->end(stream, 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     for (int rho = 0; rho <= rho_max; ++rho) {
         MwdRow row;
         row.rho = rho;

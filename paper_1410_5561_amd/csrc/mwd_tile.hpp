@@ -48,9 +48,12 @@ struct MwdGeom {
     static constexpr int NT = 64 * NWAVES;
     static_assert(NT <= 1024, "workgroup too large");
     static constexpr int Q = 2 * R + 1;             // z-queue length per level
-    static constexpr int WIN = NARR ? Q * (((L - 1) * R + 1 + Q - 1) / Q) : 1;  // coefficient ring
+    // coefficient ring: planes [s - LR, s - R] are in use at step s, and the
+    // load for plane s + 1 - R is issued during step s
+    static constexpr int WIN = NARR ? Q * (((L - 1) * R + 2 + Q - 1) / Q) : 1;
     static constexpr int U = clcm(Q, WIN);          // unroll: ring slots become constants
     static constexpr int NS = DW + 2 * R;           // LDS row slots (diamond rows + side rows)
+    static constexpr int NSX = NS + 1;              // plus a spare row for writes nobody reads
     static constexpr int S0 = U * ((R + 1 + U - 1) / U);  // step offset, multiple of U, > R
 };
 
@@ -81,10 +84,50 @@ struct MwdRow {
     int ybase;            // yL of the row's first diamond
 };
 
+// Copy the boundary band (width R around the interior) of one array into the
+// four scratch arrays, so that every array a tile loads from holds the fixed
+// boundary values.  Entry blockIdx.z of the table.
+template <typename T>
+struct HaloFill {
+    const T* src;
+    T* dst[4];
+    int nx, ny, nz, r;
+    long long sy, sz;
+};
+
+template <typename T>
+__device__ __forceinline__ void halo_fill_one(const HaloFill<T>& e)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63) - e.r;
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6) - e.r;
+    if (x >= e.nx + e.r || y >= e.ny + e.r) return;
+    const bool col_inside = x >= 0 && x < e.nx && y >= 0 && y < e.ny;
+    for (int z = -e.r; z < e.nz + e.r; ++z) {
+        if (col_inside && z == 0) z = e.nz;  // skip the interior of an interior column
+        const long long off = (long long)z * e.sz + (long long)y * e.sy + x;
+        const T v = e.src[off];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e.dst[k][off] = v;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) mwd_halo_fill_kernel(HaloFill<T> e)
+{
+    halo_fill_one(e);
+}
+
+// Batched: entry blockIdx.z of a device table.
+template <typename T>
+__global__ void __launch_bounds__(256) mwd_halo_fill_table_kernel(const HaloFill<T>* __restrict__ table)
+{
+    halo_fill_one(table[blockIdx.z]);
+}
+
 // The tile (diamond b of the row, x tile j) computed by one workgroup.
 template <int K, typename T, int DW, int WPR>
 __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row, int b, int j,
-                                         T (*ex)[MwdGeom<K, DW, WPR>::L][MwdGeom<K, DW, WPR>::NS]
+                                         T (*ex)[MwdGeom<K, DW, WPR>::L][MwdGeom<K, DW, WPR>::NSX]
                                               [MwdGeom<K, DW, WPR>::LX])
 {
     using G = MwdGeom<K, DW, WPR>;
@@ -161,12 +204,14 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     bool sv_present[R];
     const T* sv_src[R];
     int sv_y[R];
+    int side_slot[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int yrs = left_edge ? (-R + k) : (DW + k);
         sv_y[k] = yL + yrs;
         sv_present[k] = side_wave && needed(yrs, H - 1);
         sv_src[k] = level_src(sv_y[k], row.t0 + H - 1);
+        side_slot[k] = sv_present[k] ? (left_edge ? k : DW + R + k) : G::NS;  // NS: the spare row
     }
 
     T q[L + 1][Q];
@@ -188,7 +233,12 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
 
     const long long col = (long long)y * a.sy + x;
     const int s_first = -G::S0;
-    const int s_last = a.nz + R - 1 + L * R;
+    // one step past the last plane of the last level, for its delayed stores
+    const int s_last = a.nz + R + L * R;
+    // Every step issues the same global loads in the same order: a lane with
+    // nothing to load reads the interior origin of the same array instead.
+    // The scratch pairs carry a copy of the boundary values (filled before the
+    // first row), so a level's source array also serves its boundary lanes.
 
     for (int sb = s_first; sb <= s_last; sb += U) {
         static_for<0, U>([&](auto uc) {
@@ -196,88 +246,88 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             const int s = sb + u;
             const int eb = s & 1;
             // (1) publish, for every level tau < L, the plane level tau + 1
-            //     reads in-plane neighbours from at this step
+            //     reads in-plane neighbours from at this step, and the side rows
             static_for<0, L>([&](auto tc) {
                 constexpr int tau = decltype(tc)::value;
                 const int p = s - (tau + 1) * R;
                 if (((pmask >> tau) & 1u) && p >= 0 && p < a.nz)
                     ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
             });
-            if (side_wave) {
-                const int p = s - H * R;
-                if (p >= 0 && p < a.nz) {
+            // side rows: unconditional, so the wait for their loads is the
+            // same on every path; other waves write a spare row nobody reads
 #pragma unroll
-                    for (int k = 0; k < R; ++k)
-                        if (sv_present[k])
-                            ex[eb][H - 1][left_edge ? k : DW + R + k][xl] = sv[k];
-                }
-            }
+            for (int k = 0; k < R; ++k)
+                ex[eb][H - 1][side_slot[k]][xl] = sv[k];
             __syncthreads();
-            // (2) advance every level by one plane, lowest level first: level
-            //     tau reads level tau - 1's plane p + R pushed just before
+            // (2) take the values loaded during the previous step into the
+            //     queues (lanes that compute below overwrite theirs)
             static_for<0, L + 1>([&](auto tc) {
                 constexpr int tau = decltype(tc)::value;
-                const int p = s - tau * R;
-                if (((pmask >> tau) & 1u) && p >= -R && p < a.nz + R) {
-                    T v = lv[tau];
-                    if constexpr (tau >= 1) {
-                        if (((cmask >> tau) & 1u) && p >= 0 && p < a.nz) {
-                            if (xin && xl >= tau * R && xl < LX - tau * R) {
-                                auto nb = [&](int dx, int dy, int dz) -> T {
-                                    if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
-                                    if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
-                                    if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
-                                    return q[tau - 1][cmod(u - tau * R, Q)];
-                                };
-                                if constexpr (NARR > 0) {
-                                    v = apply_stencil<K, T>(nb, [&](int m) -> T {
-                                        return cr[m][cmod(u - tau * R, WIN)];
-                                    });
-                                } else {
-                                    v = apply_stencil<K, T>(nb, [&](int m) -> T { return a.w.c[m]; });
-                                }
-                            }
-                            if (((smask >> tau) & 1u) && xout)
-                                dst[tau][(long long)p * a.sz + col] = v;
-                        }
-                    }
-                    q[tau][cmod(u - tau * R, Q)] = v;
+                q[tau][cmod(u - tau * R, Q)] = lv[tau];
+            });
+            // (3) stores of the previous step (its values are still in the
+            //     queues): the last two levels of each point.  Issued before
+            //     this step's loads, so waits on those loads stay exact.
+            static_for<1, L + 1>([&](auto tc) {
+                constexpr int tau = decltype(tc)::value;
+                const int p = s - 1 - tau * R;
+                if (((smask >> tau) & 1u) && p >= 0 && p < a.nz && xout)
+                    dst[tau][(long long)p * a.sz + col] = q[tau][cmod(u - 1 - tau * R, Q)];
+            });
+            // (4) issue every global load of the next step now, unconditionally
+            //     (a lane with nothing to load reads its array's origin): level values a
+            //     tile does not compute, coefficients, side rows
+            static_for<0, L + 1>([&](auto tc) {
+                constexpr int tau = decltype(tc)::value;
+                const int pn = s - tau * R + 1;
+                const bool prange = ((pmask >> tau) & 1u) && pn >= -R && pn < a.nz + R;
+                const bool pin = pn >= 0 && pn < a.nz;
+                const bool ctype = tau >= 1 && ((cmask >> tau) & 1u);
+                const bool lact = xact & (xl >= tau * R) & (xl < LX - tau * R);
+                const bool need = prange & lact & !(ctype & xin & pin);
+                lv[tau] = src[tau][need ? (long long)pn * a.sz + col : 0LL];
+            });
+            if constexpr (NARR > 0) {
+                const int pc = s + 1 - R;
+                const bool need = (cmask != 0u) & (pc >= 0) & (pc < a.nz) & xin & (xl >= R) & (xl < LX - R);
+                const long long off = need ? (long long)pc * a.sz + col : 0LL;
+#pragma unroll
+                for (int m = 0; m < NARR; ++m) cr[m][cmod(u + 1 - R, WIN)] = a.w.arr[m][off];
+            }
+            {
+                const int ps = s + 1 - H * R;
+                const bool lane_ok = side_wave & (ps >= 0) & (ps < a.nz) & xact & (xl >= (H - 1) * R) &
+                                     (xl < LX - (H - 1) * R);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const bool need = lane_ok & sv_present[k];
+                    sv[k] = sv_src[k][need ? (long long)ps * a.sz + (long long)sv_y[k] * a.sy + x : 0LL];
                 }
-                // prefetch this level's value for the next step (plane p + 1)
-                const int pn = p + 1;
-                if (((pmask >> tau) & 1u) && pn >= -R && pn < a.nz + R) {
-                    const bool pin = pn >= 0 && pn < a.nz;
-                    const bool ctype = tau >= 1 && ((cmask >> tau) & 1u);
-                    const bool lact = xact && xl >= tau * R && xl < LX - tau * R;
-                    if (lact && !(ctype && xin && pin)) {
-                        const T* sp = (xin && pin && yin) ? src[tau] : a.halo;
-                        lv[tau] = sp[(long long)pn * a.sz + col];
+            }
+            // (5) advance every computed level by one plane, lowest level
+            //     first: level tau reads level tau - 1's plane p + R just made
+            static_for<1, L + 1>([&](auto tc) {
+                constexpr int tau = decltype(tc)::value;
+                const int p = s - tau * R;
+                if (((cmask >> tau) & 1u) && p >= 0 && p < a.nz) {
+                    if (xin && xl >= tau * R && xl < LX - tau * R) {
+                        auto nb = [&](int dx, int dy, int dz) -> T {
+                            if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
+                            if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
+                            if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
+                            return q[tau - 1][cmod(u - tau * R, Q)];
+                        };
+                        if constexpr (NARR > 0) {
+                            q[tau][cmod(u - tau * R, Q)] = apply_stencil<K, T>(nb, [&](int m) -> T {
+                                return cr[m][cmod(u - tau * R, WIN)];
+                            });
+                        } else {
+                            q[tau][cmod(u - tau * R, Q)] =
+                                apply_stencil<K, T>(nb, [&](int m) -> T { return a.w.c[m]; });
+                        }
                     }
                 }
             });
-            // (3) coefficients of plane s + 1 - R, first used by level 1 next step
-            if constexpr (NARR > 0) {
-                const int pc = s + 1 - R;
-                if (cmask != 0u && pc >= 0 && pc < a.nz && xin && xl >= R && xl < LX - R) {
-#pragma unroll
-                    for (int m = 0; m < NARR; ++m)
-                        cr[m][cmod(u + 1 - R, WIN)] = a.w.arr[m][(long long)pc * a.sz + col];
-                }
-            }
-            // (4) side rows for the next step
-            if (side_wave) {
-                const int ps = s + 1 - H * R;
-                if (ps >= 0 && ps < a.nz && xact && xl >= (H - 1) * R && xl < LX - (H - 1) * R) {
-#pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        if (sv_present[k]) {
-                            const bool inner = xin && sv_y[k] >= 0 && sv_y[k] < a.ny;
-                            const T* sp = inner ? sv_src[k] : a.halo;
-                            sv[k] = sp[(long long)ps * a.sz + (long long)sv_y[k] * a.sy + x];
-                        }
-                    }
-                }
-            }
         });
     }
 }

@@ -38,8 +38,8 @@ std::mutex g_mu;
 std::map<Key, TuneChoice> g_cache;
 bool g_file_loaded = false;
 
-constexpr int kProxyNz = 48;
-constexpr int kProxyT = 16;
+constexpr int kProxyNz = 128;
+constexpr int kProxyT = 32;
 
 const char* cache_path()
 {
