@@ -29,7 +29,7 @@ struct BatchGraph {
     BatchKey key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void* dev = nullptr;        // tiles | gargs | gvariant
+    void* dev = nullptr;        // tiles | gargs | gvariant | halo table
     void* scratch = nullptr;    // two extra buffer pairs per grid
     int ntiles = 0;
     std::vector<int> variants;  // chosen variant per grid (for reporting)
@@ -113,6 +113,8 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     }
     // 3. tile table, rows of all grids interleaved row by row (topological)
     std::vector<MwdArgs<T>> gargs(n);
+    std::vector<HaloFill<T>> halo(n);
+    int hgx = 1, hgy = 1;
     std::vector<BatchTile> tiles;
     std::vector<int> rows(n), nxt(n);
     int max_rows = 0;
@@ -129,6 +131,17 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         for (int k = 0; k < 4; ++k)
             pr[k] = reinterpret_cast<T*>(static_cast<char*>(bg.scratch) + soff[i] + k * bytes + off * es);
         fill_args<T>(gargs[i], d, hw[i], pr, T_steps);
+        HaloFill<T>& hf = halo[i];
+        hf.src = gargs[i].halo;
+        for (int k = 0; k < 4; ++k) hf.dst[k] = pr[k];
+        hf.nx = d.nx;
+        hf.ny = d.ny;
+        hf.nz = d.nz;
+        hf.r = R;
+        hf.sy = d.sy;
+        hf.sz = d.sz;
+        hgx = std::max(hgx, (d.nx + 2 * R + 63) / 64);
+        hgy = std::max(hgy, (d.ny + 2 * R + 3) / 4);
         nxt[i] = (d.nx + XT - 1) / XT;
         gargs[i].nxt = nxt[i];
         rows[i] = (T_steps + H - 1) / H + 1;  // rows 0 .. rho_max
@@ -167,8 +180,9 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     const size_t tb = tiles.size() * sizeof(BatchTile);
     const size_t ab = (size_t)n * sizeof(MwdArgs<T>);
     const size_t vb = (size_t)n * sizeof(int);
+    const size_t hb = (size_t)n * sizeof(HaloFill<T>);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    if (hipMalloc(&bg.dev, al(tb) + al(ab) + al(vb)) != hipSuccess) {
+    if (hipMalloc(&bg.dev, al(tb) + al(ab) + al(vb) + al(hb)) != hipSuccess) {
         (void)hipGetLastError();
         bg.dev = nullptr;
         *errmsg = "batched table allocation failed";
@@ -178,9 +192,11 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     BatchTile* d_tiles = reinterpret_cast<BatchTile*>(base);
     MwdArgs<T>* d_args = reinterpret_cast<MwdArgs<T>*>(base + al(tb));
     int* d_var = reinterpret_cast<int*>(base + al(tb) + al(ab));
+    HaloFill<T>* d_halo = reinterpret_cast<HaloFill<T>*>(base + al(tb) + al(ab) + al(vb));
     hipError_t e = hipMemcpy(d_tiles, tiles.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_args, gargs.data(), ab, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_var, var.data(), vb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_halo, halo.data(), hb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         *errmsg = std::string("batched table upload: ") + hipGetErrorString(e);
         return STENCIL_EDEVICE;
@@ -196,7 +212,10 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t el = hipSuccess;
+        // boundary band into the scratch pairs first (each entry checks its own extent)
+        const dim3 hgrid(hgx, hgy, n);
+        hipError_t el = sizeof(T) == 8 ? batch_halo_launch_f64(reinterpret_cast<const HaloFill<double>*>(d_halo), hgrid, cs)
+                                       : batch_halo_launch_f32(reinterpret_cast<const HaloFill<float>*>(d_halo), hgrid, cs);
         for (size_t g = 0; g + 1 < group_first.size() && el == hipSuccess; ++g) {
             const int cnt = group_first[g + 1] - group_first[g];
             if (cnt <= 0) continue;
@@ -219,8 +238,8 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
 int batch_run(int plan_kind, int plan_dtype, BatchState** state, stencil_grid* grids, const stencil_coeffs* coeffs,
               int n, int T, hipStream_t stream)
 {
-    if (!grids || !coeffs || n < 1) {
-        set_last_error("batched run needs n >= 1 grids and coefficients");
+    if (!grids || !coeffs || n < 1 || n > 65535) {
+        set_last_error("batched run needs 1 <= n <= 65535 grids and coefficients");
         return STENCIL_EINVAL;
     }
     if (T < 0) {

@@ -18,4 +18,10 @@ hipError_t batch_launch_f32(const BatchLaunch<float>& L, int nblocks, hipStream_
     return hipGetLastError();
 }
 
+hipError_t batch_halo_launch_f32(const HaloFill<float>* table, dim3 grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((mwd_halo_fill_table_kernel<float>), grid, dim3(256), 0, s, table);
+    return hipGetLastError();
+}
+
 }  // namespace mwd

@@ -18,4 +18,10 @@ hipError_t batch_launch_f64(const BatchLaunch<double>& L, int nblocks, hipStream
     return hipGetLastError();
 }
 
+hipError_t batch_halo_launch_f64(const HaloFill<double>* table, dim3 grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((mwd_halo_fill_table_kernel<double>), grid, dim3(256), 0, s, table);
+    return hipGetLastError();
+}
+
 }  // namespace mwd

@@ -48,13 +48,19 @@ struct MwdGeom {
     static constexpr int NT = 64 * NWAVES;
     static_assert(NT <= 1024, "workgroup too large");
     static constexpr int Q = 2 * R + 1;             // z-queue length per level
+    // Loads are issued PL steps before the step that consumes them, so that
+    // PL steps of compute cover the memory latency.
+    static constexpr int PL = 3;
     // coefficient ring: planes [s - LR, s - R] are in use at step s, and the
-    // load for plane s + 1 - R is issued during step s
-    static constexpr int WIN = NARR ? Q * (((L - 1) * R + 2 + Q - 1) / Q) : 1;
-    static constexpr int U = clcm(Q, WIN);          // unroll: ring slots become constants
+    // load for plane s + PD - R is in flight; the ring is rounded up to a
+    // multiple of Q and PD takes what the rounding leaves (at least 2)
+    static constexpr int WIN = NARR ? Q * (((L - 1) * R + 3 + Q - 1) / Q) : 1;
+    static constexpr int PD = NARR ? ((WIN - (L - 1) * R - 1) < PL ? (WIN - (L - 1) * R - 1) : PL) : 1;
+    static_assert(NARR == 0 || (PD >= 1 && PD + (L - 1) * R < WIN), "coefficient ring too short");
+    static constexpr int U = clcm(clcm(Q, WIN), PL);  // unroll: ring slots become constants
     static constexpr int NS = DW + 2 * R;           // LDS row slots (diamond rows + side rows)
     static constexpr int NSX = NS + 1;              // plus a spare row for writes nobody reads
-    static constexpr int S0 = U * ((R + 1 + U - 1) / U);  // step offset, multiple of U, > R
+    static constexpr int S0 = U * ((R + PL + U - 1) / U);  // step offset, multiple of U, >= R + PL
 };
 
 // Which buffer pair holds the levels written by row rho.
@@ -132,7 +138,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
 {
     using G = MwdGeom<K, DW, WPR>;
     constexpr int R = G::R, H = G::H, L = G::L, Q = G::Q, LX = G::LX, XT = G::XT;
-    constexpr int NARR = G::NARR, WIN = G::WIN, U = G::U;
+    constexpr int NARR = G::NARR, WIN = G::WIN, U = G::U, PL = G::PL;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -188,44 +194,54 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     pmask = __builtin_amdgcn_readfirstlane(pmask);
     smask = __builtin_amdgcn_readfirstlane(smask);
 
-    const T* src[L + 1];
     T* dst[L + 1];
     T* const* outp = a.pair[pair_of_row(row.rho)];
 #pragma unroll
-    for (int tau = 0; tau <= L; ++tau) {
-        src[tau] = level_src(y, row.t0 + tau);
-        dst[tau] = outp[(a.cur + row.t0 + tau) & 1];
-    }
+    for (int tau = 0; tau <= L; ++tau) dst[tau] = outp[(a.cur + row.t0 + tau) & 1];
+
+    // Edge levels: the levels of this row that the tile needs but does not
+    // compute.  On the rising side of a diamond level tau + 1 reaches R rows
+    // further out on each side than level tau, so a row is needed, before its
+    // first computed level, at the two levels just below it (fewer where the
+    // diamond is clipped); they are read from the rows below.  ta < tb.
+    const uint32_t emask = pmask & ~cmask;
+    const uint32_t erest = emask & (emask - 1u);
+    const bool has_a = emask != 0u, has_b = erest != 0u;
+    const int ta = has_a ? __builtin_ctz(emask) : 0;
+    const int tb = has_b ? __builtin_ctz(erest) : 0;
+    const T* srca = level_src(y, row.t0 + ta);
+    const T* srcb = level_src(y, row.t0 + tb);
+    // Boundary values are the same at every level: a lane outside the domain
+    // (and every lane at a boundary plane) loads level 0 from the boundary
+    // array and each higher level copies the same plane from the level below.
+    const bool lane_in = xin && yin;
+    const bool lact_a = has_a && lane_in && xl >= ta * R && xl < LX - ta * R;
+    const bool lact_b = has_b && lane_in && xl >= tb * R && xl < LX - tb * R;
+    const bool bz_act = pmask != 0u && xact;
 
     // Side rows: R rows beyond each edge of the diamond, needed only at level
-    // h - 1 by the widest level h; loaded by the edge waves straight into LDS.
-    const bool left_edge = wave_active && yr == 0, right_edge = wave_active && yr == DW - 1;
-    const bool side_wave = left_edge || right_edge;
-    bool sv_present[R];
-    const T* sv_src[R];
-    int sv_y[R];
-    int side_slot[R];
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int yrs = left_edge ? (-R + k) : (DW + k);
-        sv_y[k] = yL + yrs;
-        sv_present[k] = side_wave && needed(yrs, H - 1);
-        sv_src[k] = level_src(sv_y[k], row.t0 + H - 1);
-        side_slot[k] = sv_present[k] ? (left_edge ? k : DW + R + k) : G::NS;  // NS: the spare row
-    }
+    // h - 1 by the widest level h.  Diamond row yr < 2R loads one of them
+    // (yr < R: left side row yr - R; else right side row DW + yr - R) straight
+    // into its LDS slot; the other waves write a spare LDS row nobody reads.
+    const bool side_wave = wave_active && yr < 2 * R;
+    const int yrs = yr < R ? yr - R : DW + yr - R;
+    const int sv_y = yL + yrs;
+    const bool sv_present = side_wave && needed(yrs, H - 1);
+    const T* sv_src = level_src(sv_y, row.t0 + H - 1);
+    const int side_slot = sv_present ? yrs + R : G::NS;  // NS: the spare row
+    const bool sv_lane = sv_present && xact && xl >= (H - 1) * R && xl < LX - (H - 1) * R;
 
     T q[L + 1][Q];
-    T lv[L + 1];
-    T sv[R];
+    T lea[PL], leb[PL], bzr[PL], sv[PL];
     T cr[NARR > 0 ? NARR : 1][WIN];
 #pragma unroll
-    for (int tau = 0; tau <= L; ++tau) {
-        lv[tau] = T(0);
+    for (int tau = 0; tau <= L; ++tau)
 #pragma unroll
         for (int k = 0; k < Q; ++k) q[tau][k] = T(0);
-    }
 #pragma unroll
-    for (int k = 0; k < R; ++k) sv[k] = T(0);
+    for (int k = 0; k < PL; ++k) {
+        lea[k] = leb[k] = bzr[k] = sv[k] = T(0);
+    }
 #pragma unroll
     for (int m = 0; m < (NARR > 0 ? NARR : 1); ++m)
 #pragma unroll
@@ -235,14 +251,15 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     const int s_first = -G::S0;
     // one step past the last plane of the last level, for its delayed stores
     const int s_last = a.nz + R + L * R;
-    // Every step issues the same global loads in the same order: a lane with
-    // nothing to load reads the interior origin of the same array instead.
-    // The scratch pairs carry a copy of the boundary values (filled before the
-    // first row), so a level's source array also serves its boundary lanes.
+    // Every step issues the same global loads in the same order, each PL steps
+    // ahead of its use: a lane with nothing to load reads its array's interior
+    // origin instead, so the compiler's waits count exactly and leave the
+    // younger loads in flight.
 
     for (int sb = s_first; sb <= s_last; sb += U) {
         static_for<0, U>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
+            constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
             const int s = sb + u;
             const int eb = s & 1;
             // (1) publish, for every level tau < L, the plane level tau + 1
@@ -253,17 +270,24 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 if (((pmask >> tau) & 1u) && p >= 0 && p < a.nz)
                     ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
             });
-            // side rows: unconditional, so the wait for their loads is the
-            // same on every path; other waves write a spare row nobody reads
-#pragma unroll
-            for (int k = 0; k < R; ++k)
-                ex[eb][H - 1][side_slot[k]][xl] = sv[k];
+            // side row: unconditional, so the wait for its load is the same
+            // on every path
+            ex[eb][H - 1][side_slot][xl] = sv[k];
             __syncthreads();
-            // (2) take the values loaded during the previous step into the
-            //     queues (lanes that compute below overwrite theirs)
+            // (2) plane s - tau R of every level that is not computed here:
+            //     boundary values, or the edge levels loaded PL steps ago
+            //     (lanes that compute below overwrite theirs)
             static_for<0, L + 1>([&](auto tc) {
                 constexpr int tau = decltype(tc)::value;
-                q[tau][cmod(u - tau * R, Q)] = lv[tau];
+                const int p = s - tau * R;
+                const bool bnd = !lane_in || p < 0 || p >= a.nz;
+                T v = q[tau][cmod(u - tau * R, Q)];
+                if (has_a && ta == tau) v = lea[k];
+                if (has_b && tb == tau) v = leb[k];
+                T bv;
+                if constexpr (tau == 0) bv = bzr[k];
+                else bv = q[tau - 1][cmod(u - tau * R, Q)];
+                q[tau][cmod(u - tau * R, Q)] = bnd ? bv : v;
             });
             // (3) stores of the previous step (its values are still in the
             //     queues): the last two levels of each point.  Issued before
@@ -274,35 +298,32 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 if (((smask >> tau) & 1u) && p >= 0 && p < a.nz && xout)
                     dst[tau][(long long)p * a.sz + col] = q[tau][cmod(u - 1 - tau * R, Q)];
             });
-            // (4) issue every global load of the next step now, unconditionally
-            //     (a lane with nothing to load reads its array's origin): level values a
-            //     tile does not compute, coefficients, side rows
-            static_for<0, L + 1>([&](auto tc) {
-                constexpr int tau = decltype(tc)::value;
-                const int pn = s - tau * R + 1;
-                const bool prange = ((pmask >> tau) & 1u) && pn >= -R && pn < a.nz + R;
-                const bool pin = pn >= 0 && pn < a.nz;
-                const bool ctype = tau >= 1 && ((cmask >> tau) & 1u);
-                const bool lact = xact & (xl >= tau * R) & (xl < LX - tau * R);
-                const bool need = prange & lact & !(ctype & xin & pin);
-                lv[tau] = src[tau][need ? (long long)pn * a.sz + col : 0LL];
-            });
+            // (4) issue the loads consumed PL steps from now (PD for the
+            //     coefficients): side rows, edge levels, the boundary plane of
+            //     level 0, coefficients.  Unconditional: a lane with nothing
+            //     to load reads its array's origin.
+            {
+                const int pl = s + PL;  // level 0's plane at step s + PL
+                const int ps = pl - H * R;
+                {
+                    const bool need = sv_lane & (ps >= 0) & (ps < a.nz);
+                    sv[k] = sv_src[need ? (long long)ps * a.sz + (long long)sv_y * a.sy + x : 0LL];
+                }
+                const int pa = pl - ta * R, pb = pl - tb * R;
+                const bool na = lact_a & (pa >= 0) & (pa < a.nz);
+                const bool nb = lact_b & (pb >= 0) & (pb < a.nz);
+                lea[k] = srca[na ? (long long)pa * a.sz + col : 0LL];
+                leb[k] = srcb[nb ? (long long)pb * a.sz + col : 0LL];
+                const bool nbz = bz_act & (pl >= -R) & (pl < a.nz + R) & (!lane_in | (pl < 0) | (pl >= a.nz));
+                bzr[k] = a.halo[nbz ? (long long)pl * a.sz + col : 0LL];
+            }
             if constexpr (NARR > 0) {
-                const int pc = s + 1 - R;
+                constexpr int PD = G::PD;
+                const int pc = s + PD - R;
                 const bool need = (cmask != 0u) & (pc >= 0) & (pc < a.nz) & xin & (xl >= R) & (xl < LX - R);
                 const long long off = need ? (long long)pc * a.sz + col : 0LL;
 #pragma unroll
-                for (int m = 0; m < NARR; ++m) cr[m][cmod(u + 1 - R, WIN)] = a.w.arr[m][off];
-            }
-            {
-                const int ps = s + 1 - H * R;
-                const bool lane_ok = side_wave & (ps >= 0) & (ps < a.nz) & xact & (xl >= (H - 1) * R) &
-                                     (xl < LX - (H - 1) * R);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const bool need = lane_ok & sv_present[k];
-                    sv[k] = sv_src[k][need ? (long long)ps * a.sz + (long long)sv_y[k] * a.sy + x : 0LL];
-                }
+                for (int m = 0; m < NARR; ++m) cr[m][cmod(u + PD - R, WIN)] = a.w.arr[m][off];
             }
             // (5) advance every computed level by one plane, lowest level
             //     first: level tau reads level tau - 1's plane p + R just made

@@ -255,9 +255,11 @@ MwdShape tune_batch_shape(int kind, int dtype, int nx, int ny, int nz, int T)
     if (tune_generic(kind, dtype, bucket(nx), bucket(ny), bucket(nz), T, true, &c) == STENCIL_OK &&
         c.mode == STENCIL_MODE_MWD)
         return c.shape;
-    if (kind == K25C || kind == K25V) return MwdShape{16, 1};
-    if (kind == K7V) return MwdShape{4, 4};
-    return MwdShape{8, 2};
+    // the first compiled variant of this kind
+    const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
+    for (int i = 0; i < nv; ++i)
+        if (kBatchVariantInfo[i].kind == kind) return MwdShape{kBatchVariantInfo[i].dw, kBatchVariantInfo[i].wpr};
+    return MwdShape{0, 0};
 }
 
 }  // namespace mwd
