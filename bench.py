@@ -210,6 +210,14 @@ def main():
     avg_launch_s = prof["main_ms"] / 1e3 / main_launches
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9
     mode_name = {0: "auto", 1: "naive", 2: "mwd"}[desc["mode"]]
+    kname = "mwd_row_kernel" if mode_name == "mwd" else "naive_sweep_kernel"
+    shape = "%dx%d" % (desc["dw"], desc["lanes"]) if mode_name == "mwd" else "naive"
+    # measured HBM bytes per launch, from the committed rocprofv3 counter
+    # summary of this kernel, workload and shape (None once the sources changed)
+    from paper_1410_5561_amd import profiling
+    traffic = profiling.traffic_for(kname, w["name"], dtype, shape)
+    if traffic is not None:
+        traffic = round(traffic)
     out = {
         "metric": "GLUP/s + rocprof bytes/LUP, MWD vs naive sweep, FP64 and FP32, 1 GPU",
         "value": round(value, 3),
@@ -229,8 +237,9 @@ def main():
                      "xtile": desc["xtile"], "levels": desc["levels"]},
         "model_bytes_per_lup": round(model_bpl, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "mwd_row_kernel" if mode_name == "mwd" else "naive_sweep_kernel",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kname,
+                     "algorithmic_bytes_per_launch": round(alg_bytes_per_launch),
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches_per_step": prof["main_launches"] // a.steps,
                      "other_kernels_ms_per_step": round(prof["other_ms"] / a.steps, 4)},

@@ -50,6 +50,9 @@ struct BatchState {
 
 static size_t es_of(int dtype) { return dtype == 0 ? 8 : 4; }
 
+// run of adjacent tiles given to one XCD in a batched row group
+constexpr int kBatchXcdRun = 4;
+
 static int variant_index(int kind, int dtype, const MwdShape& s)
 {
     const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
@@ -149,7 +152,8 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     }
     std::vector<int> group_first;  // table index where each row group starts
     for (int rho = 0; rho < max_rows; ++rho) {
-        group_first.push_back((int)tiles.size());
+        const size_t gstart = tiles.size();
+        group_first.push_back((int)gstart);
         // larger grids first within a group
         std::vector<int> order;
         for (int i = 0; i < n; ++i)
@@ -167,6 +171,11 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
                 for (int j = 0; j < nxt[i]; ++j)
                     tiles.push_back(BatchTile{i, 0, rho, (rho - 1) * H, ybase, b, j, 0});
         }
+        // workgroup k of the group runs entry k; place runs of adjacent x
+        // tiles on one XCD (as the row kernel does)
+        const int cnt = (int)(tiles.size() - gstart);
+        std::vector<BatchTile> g(tiles.begin() + gstart, tiles.end());
+        for (int k = 0; k < cnt; ++k) tiles[gstart + k] = g[xcd_tile(k, cnt, kBatchXcdRun)];
     }
     // the gather of every grid's last two levels
     group_first.push_back((int)tiles.size());

@@ -94,7 +94,7 @@ int mwd_levels(int kind, const MwdShape& s);
 // All compiled shapes for (kind, dtype); returns how many were written.
 int mwd_shapes(int kind, int dtype, MwdShape* out, int cap);
 // Whether the shape's row kernel keeps values in scratch memory (register spill).
-hipError_t mwd_kernel_spills(int kind, int dtype, const MwdShape& s, bool* spills);
+hipError_t mwd_kernel_scratch(int kind, int dtype, const MwdShape& s, size_t* bytes_per_lane);
 int mwd_xtile(int kind, const MwdShape& s);
 
 // Run T steps with MWD.  `scratch` holds two extra grid-sized buffer pairs

@@ -48,14 +48,14 @@ int mwd_shapes(int kind, int dtype, MwdShape* out, int cap)
     return n;
 }
 
-hipError_t mwd_kernel_spills(int kind, int dtype, const MwdShape& s, bool* spills)
+hipError_t mwd_kernel_scratch(int kind, int dtype, const MwdShape& s, size_t* bytes_per_lane)
 {
     const MwdEntry* e = find_entry(kind, dtype, s);
     if (!e) return hipErrorInvalidValue;
     hipFuncAttributes fa;
     hipError_t err = hipFuncGetAttributes(&fa, e->kernel);
     if (err != hipSuccess) return err;
-    *spills = fa.localSizeBytes > 0;
+    *bytes_per_lane = fa.localSizeBytes;
     return hipSuccess;
 }
 

@@ -13,10 +13,9 @@ __global__ void __launch_bounds__(64 * DW * WPR)
 mwd_row_kernel(MwdArgs<T> a, MwdRow row)
 {
     using G = MwdGeom<K, DW, WPR>;
-    __shared__ T ex[2][G::L][G::NSX][G::LX];
-    const int b = blockIdx.x / a.nxt;
-    const int j = blockIdx.x % a.nxt;
-    mwd_tile<K, T, DW, WPR>(a, row, b, j, ex);
+    __shared__ T ex[2][G::L][G::NSX][G::LXP];
+    const int t = xcd_tile(blockIdx.x, gridDim.x, a.nxt);
+    mwd_tile<K, T, DW, WPR>(a, row, t / a.nxt, t % a.nxt, ex);
 }
 
 // After the last row, copy u_T and u_{T-1} of every point out of the pair

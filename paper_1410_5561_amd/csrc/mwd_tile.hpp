@@ -60,8 +60,32 @@ struct MwdGeom {
     static constexpr int U = clcm(clcm(Q, WIN), PL);  // unroll: ring slots become constants
     static constexpr int NS = DW + 2 * R;           // LDS row slots (diamond rows + side rows)
     static constexpr int NSX = NS + 1;              // plus a spare row for writes nobody reads
+    static constexpr int LXP = LX + 2 * R;          // LDS row: the lanes plus R on each side
     static constexpr int S0 = U * ((R + PL + U - 1) / U);  // step offset, multiple of U, >= R + PL
 };
+
+// A value the compiler must recompute where it is used (it passes through a
+// vector register): keeps per-step offsets (a compile-time step times a
+// run-time stride) from being hoisted out of the chunk loop, where they would
+// hold one register each for the whole loop.
+__device__ __forceinline__ uint32_t opaque_u32(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// The same for a wave-uniform value that stays in a scalar register: stops
+// loop strength reduction from turning every per-step address of the cold
+// (boundary) steps into an induction variable of its own.
+__device__ __forceinline__ int opaque_uniform(int v)
+{
+    asm volatile("" : "+v"(v));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// An empty side effect: a branch around it stays a branch instead of
+// becoming per-lane selects.
+__device__ __forceinline__ void keep_branch() { asm volatile(""); }
 
 // Which buffer pair holds the levels written by row rho.
 __host__ __device__ __forceinline__ int pair_of_row(int rho) { return (rho + 1) % 3; }
@@ -83,6 +107,22 @@ struct MwdArgs {
     int nsteps;           // total number of time steps of the run
     int nxt;              // x tiles per diamond
 };
+
+// Tile of workgroup blk in a launch of ntiles tiles t = b * nxt + j.
+// Workgroups go to the eight XCDs round-robin (block i to XCD i mod 8), each
+// XCD with its own L2.  The x tiles of one diamond overlap by 2LR columns and
+// share the cache lines at their ends, so runs of c consecutive tiles go to
+// one XCD, where the second read of a shared line can hit in L2.  The last,
+// partial group of 8c tiles keeps the identity; the map is a bijection.
+__host__ __device__ __forceinline__ int xcd_tile(int blk, int ntiles, int c)
+{
+    constexpr int NXCD = 8;
+    const int gsz = NXCD * c;
+    const int g = blk / gsz;
+    if ((g + 1) * gsz > ntiles) return blk;
+    const int r = blk - g * gsz;
+    return g * gsz + (r % NXCD) * c + r / NXCD;
+}
 
 // One diamond row of the schedule.
 struct MwdRow {
@@ -134,7 +174,7 @@ __global__ void __launch_bounds__(256) mwd_halo_fill_table_kernel(const HaloFill
 template <int K, typename T, int DW, int WPR>
 __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row, int b, int j,
                                          T (*ex)[MwdGeom<K, DW, WPR>::L][MwdGeom<K, DW, WPR>::NSX]
-                                              [MwdGeom<K, DW, WPR>::LX])
+                                              [MwdGeom<K, DW, WPR>::LXP])
 {
     using G = MwdGeom<K, DW, WPR>;
     constexpr int R = G::R, H = G::H, L = G::L, Q = G::Q, LX = G::LX, XT = G::XT;
@@ -215,9 +255,6 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     // (and every lane at a boundary plane) loads level 0 from the boundary
     // array and each higher level copies the same plane from the level below.
     const bool lane_in = xin && yin;
-    const bool lact_a = has_a && lane_in && xl >= ta * R && xl < LX - ta * R;
-    const bool lact_b = has_b && lane_in && xl >= tb * R && xl < LX - tb * R;
-    const bool bz_act = pmask != 0u && xact;
 
     // Side rows: R rows beyond each edge of the diamond, needed only at level
     // h - 1 by the widest level h.  Diamond row yr < 2R loads one of them
@@ -229,7 +266,6 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     const bool sv_present = side_wave && needed(yrs, H - 1);
     const T* sv_src = level_src(sv_y, row.t0 + H - 1);
     const int side_slot = sv_present ? yrs + R : G::NS;  // NS: the spare row
-    const bool sv_lane = sv_present && xact && xl >= (H - 1) * R && xl < LX - (H - 1) * R;
 
     T q[L + 1][Q];
     T lea[PL], leb[PL], bzr[PL], sv[PL];
@@ -251,32 +287,79 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     const int s_first = -G::S0;
     // one step past the last plane of the last level, for its delayed stores
     const int s_last = a.nz + R + L * R;
-    // Every step issues the same global loads in the same order, each PL steps
-    // ahead of its use: a lane with nothing to load reads its array's interior
-    // origin instead, so the compiler's waits count exactly and leave the
-    // younger loads in flight.
 
-    for (int sb = s_first; sb <= s_last; sb += U) {
-        static_for<0, U>([&](auto uc) {
-            constexpr int u = decltype(uc)::value;
-            constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
-            const int s = sb + u;
-            const int eb = s & 1;
-            // (1) publish, for every level tau < L, the plane level tau + 1
-            //     reads in-plane neighbours from at this step, and the side rows
+    // Steady state: the steps s in [LR + 1, nz - PL) touch only planes inside
+    // the domain (every level's plane, every load and every store), so they
+    // run without plane checks.  They are taken in whole chunks of U steps,
+    // and only while U + LR + 1 planes span less than 4 GiB, so that a chunk
+    // can address each array through one 64-bit base and 32-bit lane offsets.
+    const long long szb = a.sz * (long long)sizeof(T);
+    const bool fast_ok = (long long)(U + L * R + 1) * szb < (1LL << 32);
+    const int s_fast_begin = fast_ok ? U * ((L * R + 1 + U - 1) / U) : s_first;
+    const int s_fast_end = fast_ok ? max(s_fast_begin, U * floordiv(a.nz - PL, U)) : s_first;
+    // does any lane of this wave stand for a point outside the domain?
+    const bool wave_bnd = __any(wave_active && xact && !lane_in && pmask != 0u);
+    // lane byte offsets from the plane corner (x, y) = (-R, -R); 0 for a
+    // lane with nothing to load (it then reads the corner)
+    const long long corner = (long long)R * a.sy + R;
+    const bool col_ok = xact && y >= -R && y < a.ny + R;
+    const uint32_t colb = col_ok ? (uint32_t)((col + corner) * (long long)sizeof(T)) : 0u;
+    const uint32_t off_s = sv_present && xact
+                               ? (uint32_t)(((long long)(sv_y + R) * a.sy + x + R) * (long long)sizeof(T))
+                               : 0u;
+    // byte address of the corner of plane p of an array
+    auto plane = [&](const T* arr, int p) -> const char* {
+        return reinterpret_cast<const char*>(arr) + ((long long)p * a.sz - corner) * (long long)sizeof(T);
+    };
+    auto ld = [](const char* base, uint32_t off) -> T { return *reinterpret_cast<const T*>(base + off); };
+    const int par0 = (a.cur + row.t0) & 1;  // buffer of the even levels
+    const int ea = has_a ? ta : -1, eb_ = has_b ? tb : -1;  // edge levels, -1: none
+
+    // One wavefront step.  FAST: a steady-state step (see above).
+    auto step = [&](auto uc, auto fc, int s, const char* const* cb) {
+        constexpr int u = decltype(uc)::value;
+        constexpr bool FAST = decltype(fc)::value;
+        constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
+        const int eb = s & 1;
+        // (1) publish, for every level tau < L, the plane level tau + 1 reads
+        //     in-plane neighbours from at this step, and the side row.  In the
+        //     steady state a level this row does not hold publishes too: no
+        //     other row reads that slot.
+        static_for<0, L>([&](auto tc) {
+            constexpr int tau = decltype(tc)::value;
+            const int p = s - (tau + 1) * R;
+            if (FAST || (((pmask >> tau) & 1u) && p >= 0 && p < a.nz))
+                ex[eb][tau][yr + R][xl + R] = q[tau][cmod(u - (tau + 1) * R, Q)];
+        });
+        // side row: unconditional, so the wait for its load is the same on
+        // every path
+        ex[eb][H - 1][side_slot][xl + R] = sv[k];
+        __syncthreads();
+        // (2) plane s - tau R of every level that is not computed here:
+        //     boundary values, or the edge levels loaded PL steps ago (lanes
+        //     that compute below overwrite theirs)
+        if constexpr (FAST) {
+            // uniform branches (kept as branches: no per-level lane masks)
             static_for<0, L>([&](auto tc) {
                 constexpr int tau = decltype(tc)::value;
-                const int p = s - (tau + 1) * R;
-                if (((pmask >> tau) & 1u) && p >= 0 && p < a.nz)
-                    ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
+                if (ea == tau) {
+                    keep_branch();
+                    q[tau][cmod(u - tau * R, Q)] = lea[k];
+                } else if (eb_ == tau) {
+                    keep_branch();
+                    q[tau][cmod(u - tau * R, Q)] = leb[k];
+                }
             });
-            // side row: unconditional, so the wait for its load is the same
-            // on every path
-            ex[eb][H - 1][side_slot][xl] = sv[k];
-            __syncthreads();
-            // (2) plane s - tau R of every level that is not computed here:
-            //     boundary values, or the edge levels loaded PL steps ago
-            //     (lanes that compute below overwrite theirs)
+            if (wave_bnd) {
+                static_for<0, L + 1>([&](auto tc) {
+                    constexpr int tau = decltype(tc)::value;
+                    T bv;
+                    if constexpr (tau == 0) bv = bzr[k];
+                    else bv = q[tau - 1][cmod(u - tau * R, Q)];
+                    if (!lane_in) q[tau][cmod(u - tau * R, Q)] = bv;
+                });
+            }
+        } else {
             static_for<0, L + 1>([&](auto tc) {
                 constexpr int tau = decltype(tc)::value;
                 const int p = s - tau * R;
@@ -289,68 +372,130 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 else bv = q[tau - 1][cmod(u - tau * R, Q)];
                 q[tau][cmod(u - tau * R, Q)] = bnd ? bv : v;
             });
-            // (3) stores of the previous step (its values are still in the
-            //     queues): the last two levels of each point.  Issued before
-            //     this step's loads, so waits on those loads stay exact.
-            static_for<1, L + 1>([&](auto tc) {
-                constexpr int tau = decltype(tc)::value;
-                const int p = s - 1 - tau * R;
-                if (((smask >> tau) & 1u) && p >= 0 && p < a.nz && xout)
-                    dst[tau][(long long)p * a.sz + col] = q[tau][cmod(u - 1 - tau * R, Q)];
-            });
-            // (4) issue the loads consumed PL steps from now (PD for the
-            //     coefficients): side rows, edge levels, the boundary plane of
-            //     level 0, coefficients.  Unconditional: a lane with nothing
-            //     to load reads its array's origin.
-            {
-                const int pl = s + PL;  // level 0's plane at step s + PL
-                const int ps = pl - H * R;
-                {
-                    const bool need = sv_lane & (ps >= 0) & (ps < a.nz);
-                    sv[k] = sv_src[need ? (long long)ps * a.sz + (long long)sv_y * a.sy + x : 0LL];
+        }
+        // (3) stores of the previous step (its values are still in the
+        //     queues): the last two levels of each point.  Issued before this
+        //     step's loads, so waits on those loads stay exact.
+        static_for<1, L + 1>([&](auto tc) {
+            constexpr int tau = decltype(tc)::value;
+            const int p = s - 1 - tau * R;
+            if constexpr (FAST) {
+                // cb[4 + (tau & 1)]: corner of plane sb - 1 - LR of the
+                // buffer that holds level tau
+                if (((smask >> tau) & 1u) && xout) {
+                    char* base = const_cast<char*>(cb[4 + (tau & 1)]);
+                    const uint32_t off = colb + opaque_u32((uint32_t)((u + (L - tau) * R) * szb));
+                    *reinterpret_cast<T*>(base + off) = q[tau][cmod(u - 1 - tau * R, Q)];
                 }
-                const int pa = pl - ta * R, pb = pl - tb * R;
-                const bool na = lact_a & (pa >= 0) & (pa < a.nz);
-                const bool nb = lact_b & (pb >= 0) & (pb < a.nz);
-                lea[k] = srca[na ? (long long)pa * a.sz + col : 0LL];
-                leb[k] = srcb[nb ? (long long)pb * a.sz + col : 0LL];
-                const bool nbz = bz_act & (pl >= -R) & (pl < a.nz + R) & (!lane_in | (pl < 0) | (pl >= a.nz));
-                bzr[k] = a.halo[nbz ? (long long)pl * a.sz + col : 0LL];
+            } else {
+                if (((smask >> tau) & 1u) && p >= 0 && p < a.nz && xout)
+                    *reinterpret_cast<T*>(const_cast<char*>(plane(dst[tau], p)) + colb) =
+                        q[tau][cmod(u - 1 - tau * R, Q)];
             }
+        });
+        // (4) issue the loads consumed PL steps from now (PD for the
+        //     coefficients): side row, edge levels, the boundary plane of
+        //     level 0, coefficients.  A wave issues the loads it can need on
+        //     every step it can need them; each lane reads its own column
+        //     (lanes whose value nobody uses read valid neighbouring data).
+        if constexpr (FAST) {
+            // cb[0..3]: corners of the chunk's first planes of the side row,
+            // edge level a, edge level b and the boundary array; cb[6 + m]:
+            // coefficient array m
+            const uint32_t du = opaque_u32((uint32_t)(u * szb));
+            const uint32_t o = colb + du;
+            if (sv_present) sv[k] = ld(cb[0], off_s + du);
+            if (has_a) lea[k] = ld(cb[1], o);
+            if (has_b) leb[k] = ld(cb[2], o);
+            if (wave_bnd) bzr[k] = ld(cb[3], o);
+            if constexpr (NARR > 0) {
+                constexpr int PD = G::PD;
+                if (cmask != 0u) {
+#pragma unroll
+                    for (int m = 0; m < NARR; ++m) cr[m][cmod(u + PD - R, WIN)] = ld(cb[6 + m], o);
+                }
+            }
+        } else {
+            // a stream whose plane lies outside its range loads, on every
+            // lane, the corner of the nearest plane inside it
+            auto gld = [&](const T* arr, int p, int lo, int hi, uint32_t off) -> T {
+                const bool in = p >= lo && p < hi;
+                return ld(plane(arr, min(max(p, lo), hi - 1)), in ? off : 0u);
+            };
+            const int pl = s + PL;  // level 0's plane at step s + PL
+            if (sv_present) sv[k] = gld(sv_src, pl - H * R, 0, a.nz, off_s);
+            if (has_a) lea[k] = gld(srca, pl - ta * R, 0, a.nz, colb);
+            if (has_b) leb[k] = gld(srcb, pl - tb * R, 0, a.nz, colb);
+            // boundary values: at boundary planes every lane needs them, at
+            // other planes the lanes outside the domain
+            const bool pbnd = pl < 0 || pl >= a.nz;
+            if (pmask != 0u && (wave_bnd || pbnd)) bzr[k] = gld(a.halo, pl, -R, a.nz + R, colb);
             if constexpr (NARR > 0) {
                 constexpr int PD = G::PD;
                 const int pc = s + PD - R;
-                const bool need = (cmask != 0u) & (pc >= 0) & (pc < a.nz) & xin & (xl >= R) & (xl < LX - R);
-                const long long off = need ? (long long)pc * a.sz + col : 0LL;
+                if (cmask != 0u) {
 #pragma unroll
-                for (int m = 0; m < NARR; ++m) cr[m][cmod(u + PD - R, WIN)] = a.w.arr[m][off];
+                    for (int m = 0; m < NARR; ++m)
+                        cr[m][cmod(u + PD - R, WIN)] = gld(a.w.arr[m], pc, 0, a.nz, colb);
+                }
             }
-            // (5) advance every computed level by one plane, lowest level
-            //     first: level tau reads level tau - 1's plane p + R just made
-            static_for<1, L + 1>([&](auto tc) {
-                constexpr int tau = decltype(tc)::value;
-                const int p = s - tau * R;
-                if (((cmask >> tau) & 1u) && p >= 0 && p < a.nz) {
-                    if (xin && xl >= tau * R && xl < LX - tau * R) {
-                        auto nb = [&](int dx, int dy, int dz) -> T {
-                            if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
-                            if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
-                            if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
-                            return q[tau - 1][cmod(u - tau * R, Q)];
-                        };
-                        if constexpr (NARR > 0) {
-                            q[tau][cmod(u - tau * R, Q)] = apply_stencil<K, T>(nb, [&](int m) -> T {
-                                return cr[m][cmod(u - tau * R, WIN)];
-                            });
-                        } else {
-                            q[tau][cmod(u - tau * R, Q)] =
-                                apply_stencil<K, T>(nb, [&](int m) -> T { return a.w.c[m]; });
-                        }
+        }
+        // (5) advance every computed level by one plane, lowest level first:
+        //     level tau reads level tau - 1's plane p + R just made.  In the
+        //     steady state every lane computes (lanes outside the level's
+        //     range produce values nobody reads) and lanes outside the domain
+        //     then take the boundary value back.
+        static_for<1, L + 1>([&](auto tc) {
+            constexpr int tau = decltype(tc)::value;
+            const int p = s - tau * R;
+            if (((cmask >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
+                if (FAST || (xin && xl >= tau * R && xl < LX - tau * R)) {
+                    auto nb = [&](int dx, int dy, int dz) -> T {
+                        if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
+                        if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl + R];
+                        if (dx != 0) return ex[eb][tau - 1][yr + R][xl + R + dx];
+                        return q[tau - 1][cmod(u - tau * R, Q)];
+                    };
+                    if constexpr (NARR > 0) {
+                        q[tau][cmod(u - tau * R, Q)] = apply_stencil<K, T>(nb, [&](int m) -> T {
+                            return cr[m][cmod(u - tau * R, WIN)];
+                        });
+                    } else {
+                        q[tau][cmod(u - tau * R, Q)] =
+                            apply_stencil<K, T>(nb, [&](int m) -> T { return a.w.c[m]; });
                     }
                 }
-            });
+                if constexpr (FAST) {
+                    if (wave_bnd && !lane_in) q[tau][cmod(u - tau * R, Q)] = q[tau - 1][cmod(u - tau * R, Q)];
+                }
+            }
         });
+    };
+
+    const char* const nocb[1] = {nullptr};
+    auto generic_chunks = [&](int from, int to) {
+        for (int sb = from; sb < to; sb += U)
+            static_for<0, U>([&](auto uc) {
+                step(uc, std::false_type{}, opaque_uniform(sb + decltype(uc)::value), nocb);
+            });
+    };
+    generic_chunks(s_first, s_fast_begin);
+    for (int sb = s_fast_begin; sb < s_fast_end; sb += U) {
+        const int pl = sb + PL;
+        const char* cb[6 + (NARR > 0 ? NARR : 1)];
+        cb[0] = plane(sv_src, pl - H * R);
+        cb[1] = plane(srca, pl - ta * R);
+        cb[2] = plane(srcb, pl - tb * R);
+        cb[3] = plane(a.halo, pl);
+        cb[4] = plane(a.pair[pair_of_row(row.rho)][par0], sb - 1 - L * R);
+        cb[5] = plane(a.pair[pair_of_row(row.rho)][par0 ^ 1], sb - 1 - L * R);
+        if constexpr (NARR > 0) {
+#pragma unroll
+            for (int m = 0; m < NARR; ++m) cb[6 + m] = plane(a.w.arr[m], sb + G::PD - R);
+        }
+        static_for<0, U>([&](auto uc) { step(uc, std::true_type{}, sb + decltype(uc)::value, cb); });
     }
+    generic_chunks(s_fast_end, s_last + 1);
 }
 
 }  // namespace mwd

@@ -3,7 +3,7 @@
 // extent, in the spirit of the paper's auto-tuning of diamond width, frontlines
 // and x-tile (Sec. II-A, Sec. IV-B).  The search space is pruned to shapes
 // whose tile kernel holds its working set in registers and LDS (a shape that
-// spills to scratch memory is not tried), the analogue of keeping the cache
+// spills more than a few registers to scratch memory is not tried), the analogue of keeping the cache
 // block inside the cache (Sec. III-B).  Choices are cached per device and
 // size bucket for the life of the process and, if MWD_TUNE_CACHE names a
 // file, across processes.
@@ -39,6 +39,9 @@ std::map<Key, TuneChoice> g_cache;
 bool g_file_loaded = false;
 
 constexpr int kProxyNz = 128;
+// A tile kernel that spills more than this to scratch memory (bytes per lane)
+// is not tried; a few spilled registers outside the step loop cost little.
+constexpr size_t kMaxSpillBytes = 32;
 constexpr int kProxyT = 32;
 
 const char* cache_path()
@@ -207,13 +210,15 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch,
         MwdShape shapes[16];
         const int ns = mwd_shapes(kind, dtype, shapes, 16);
         for (int i = 0; i < ns; ++i) {
-            bool spills = false;
-            if (mwd_kernel_spills(kind, dtype, shapes[i], &spills) == hipSuccess && !spills)
+            size_t scratch = 0;
+            if (mwd_kernel_scratch(kind, dtype, shapes[i], &scratch) == hipSuccess && scratch <= kMaxSpillBytes)
                 cands.push_back(TuneChoice{STENCIL_MODE_MWD, shapes[i]});
         }
     }
     if (cands.empty()) return STENCIL_EUNSUPPORTED;
     TuneChoice best = cands[0];
+    const char* ve = std::getenv("MWD_TUNE_VERBOSE");
+    const bool verbose = ve && *ve && *ve != '0';
     if (cands.size() > 1) {
         Proxy P;
         hipStream_t s = nullptr;
@@ -223,6 +228,10 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch,
                 // a batched shape is timed through the row kernel of the same tile
                 if (c.mode == STENCIL_MODE_MWD && !mwd_supported(kind, dtype, c.shape)) continue;
                 const double ms = time_choice(P, Tp, c, s);
+                if (verbose)
+                    std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d T=%d%s: %s dw %d lanes %d: %.3f ms\n",
+                                 kind, dtype, nx, ny, nzp, Tp, batch ? " (batched)" : "",
+                                 c.mode == STENCIL_MODE_NAIVE ? "naive" : "mwd", c.shape.dw, c.shape.wpr * 64, ms);
                 if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
                     best_ms = ms;
                     best = c;

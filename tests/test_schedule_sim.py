@@ -81,3 +81,87 @@ def test_every_point_in_exactly_one_tile():
                             seen[y, t] += 1
                             assert mwd_sim.row_of(y, t, R, DW) == rho
         assert (seen[:, 1:] == 1).all()
+
+
+def _tile_masks(R, DW, ny, T, rho, b):
+    """Per diamond row yr of tile (rho, b): the computed and present level
+    masks, and the side-row presence, in the HIP tile kernel's terms."""
+    H = DW // (2 * R)
+    L = 2 * H - 1
+    t0 = (rho - 1) * H
+    yoff = (rho % 2) * (DW // 2)
+    ybase = yoff - DW if yoff > 0 else 0
+    yL = ybase + b * DW
+
+    def computed(yrr, tau):
+        if tau < 1 or tau > L or yrr < 0 or yrr >= DW:
+            return False
+        t = t0 + tau
+        if t < 1 or t > T:
+            return False
+        if not 0 <= yL + yrr < ny:
+            return False
+        d = DW // 2 - 1 - yrr if yrr < DW // 2 else yrr - DW // 2
+        return d < R * min(tau, 2 * H - tau)
+
+    def needed(yrr, tau):
+        return tau < L and any(computed(yrr + dy, tau + 1) for dy in range(-R, R + 1))
+
+    out = []
+    for yr in range(DW):
+        c = [computed(yr, tau) for tau in range(L + 1)]
+        p = [c[tau] or needed(yr, tau) for tau in range(L + 1)]
+        out.append((c, p))
+    side = {yrs: any(needed(yrs, tau) for tau in range(L + 1) if tau != H - 1)
+            for yrs in list(range(-R, 0)) + list(range(DW, DW + R))}
+    return out, side, yL
+
+
+@pytest.mark.parametrize("R,DW", [(1, 4), (1, 6), (1, 8), (1, 12), (1, 16), (4, 8), (4, 16), (4, 24)])
+def test_edge_levels_at_most_two(R, DW):
+    """The tile kernel loads, per diamond row, only the (at most two) levels
+    below its first computed level that the tile needs, plus the boundary;
+    side rows are needed at level h - 1 only.  Checked over every row and
+    diamond, with clipping at t = 1, t = T and both y edges."""
+    H = DW // (2 * R)
+    for ny in (DW // 2 + 1, 3 * DW + 5, 40):
+        for T in (1, H, 2 * H + 1, 3 * H + 2):
+            for rho in range(-(-T // H) + 1):
+                yoff = (rho % 2) * (DW // 2)
+                ybase = yoff - DW if yoff > 0 else 0
+                for b in range((ny - 1 - ybase) // DW + 1):
+                    rows, side, yL = _tile_masks(R, DW, ny, T, rho, b)
+                    for yr, (c, p) in enumerate(rows):
+                        if not 0 <= yL + yr < ny:
+                            # a row outside the domain holds boundary values
+                            # at every level it is present at
+                            assert not any(c)
+                            continue
+                        edge = [tau for tau in range(len(c)) if p[tau] and not c[tau]]
+                        assert len(edge) <= 2, (R, DW, ny, T, rho, b, yr, edge)
+                        if edge and any(c):
+                            first = c.index(True)
+                            assert all(tau < first for tau in edge)
+                    # side rows are never needed at a level other than h - 1
+                    assert not any(side.values())
+
+
+def _xcd_tile(blk, ntiles, c):
+    # the tile kernel's workgroup-to-tile map (XCD-aware, see mwd_tile.hpp)
+    g = blk // (8 * c)
+    if (g + 1) * 8 * c > ntiles:
+        return blk
+    r = blk - g * 8 * c
+    return g * 8 * c + (r % 8) * c + r // 8
+
+
+@pytest.mark.parametrize("ntiles,c", [(1, 1), (7, 3), (64 * 11, 11), (128 * 9, 9), (100, 13), (8 * 5 * 3 + 4, 5)])
+def test_xcd_tile_map_is_bijection_with_runs_per_xcd(ntiles, c):
+    t = [_xcd_tile(b, ntiles, c) for b in range(ntiles)]
+    assert sorted(t) == list(range(ntiles))
+    # inside full groups, consecutive tiles of a run share the XCD (blk mod 8)
+    full = (ntiles // (8 * c)) * 8 * c
+    inv = {tt: b for b, tt in enumerate(t)}
+    for tt in range(full):
+        if tt % c != c - 1:
+            assert inv[tt] % 8 == inv[tt + 1] % 8
