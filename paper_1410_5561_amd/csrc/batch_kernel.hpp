@@ -61,7 +61,7 @@ struct BatchKernelShapes {
     template <class Vv>
     static constexpr size_t lds_of() {
         using G = MwdGeom<Vv::kind, Vv::dw, Vv::wpr>;
-        return sizeof(T) * 2 * G::L * G::NSX * G::LXP;
+        return sizeof(T) * 2 * G::L * G::NSX * G::LX;
     }
     static constexpr size_t lds_bytes() {
         size_t m = 16;
@@ -81,7 +81,7 @@ __device__ __forceinline__ void batch_dispatch(int variant, const MwdArgs<T>& a,
             batch_gather<T, G::R, V::dw>(a, t.b, t.j);
         } else {
             mwd_tile<V::kind, T, V::dw, V::wpr>(
-                a, row, t.b, t.j, reinterpret_cast<T (*)[G::L][G::NSX][G::LXP]>(lds));
+                a, row, t.b, t.j, reinterpret_cast<T (*)[G::L][G::NSX][G::LX]>(lds));
         }
         return;
     }

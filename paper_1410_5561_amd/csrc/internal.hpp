@@ -101,6 +101,10 @@ int mwd_xtile(int kind, const MwdShape& s);
 // (4 pointers at the interior origin, same strides as g).
 hipError_t mwd_run(const DevGrid& g, const HostWeights& w, int T, const MwdShape& s,
                    void* const scratch[4], hipStream_t stream, Prof* prof);
+// Rows [rho_lo, rho_hi] of the schedule only, without the boundary fill and
+// the gather: for timing (the tuner), not for results.
+hipError_t mwd_run_rows(const DevGrid& g, const HostWeights& w, int T, const MwdShape& s, void* const scratch[4],
+                        hipStream_t stream, int rho_lo, int rho_hi);
 
 // FP64 norms: which 0 -> of a, which 1 -> of a - b (b may be another dtype).
 hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b,

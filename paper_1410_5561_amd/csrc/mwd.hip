@@ -68,7 +68,15 @@ hipError_t mwd_run(const DevGrid& g, const HostWeights& w, int T, const MwdShape
 {
     const MwdEntry* e = find_entry(w.kind, g.dtype, s);
     if (!e) return hipErrorInvalidValue;
-    return e->fn(g, w, T, scratch, stream, prof);
+    return e->fn(g, w, T, scratch, stream, prof, 0, 1 << 30);
+}
+
+hipError_t mwd_run_rows(const DevGrid& g, const HostWeights& w, int T, const MwdShape& s, void* const scratch[4],
+                        hipStream_t stream, int rho_lo, int rho_hi)
+{
+    const MwdEntry* e = find_entry(w.kind, g.dtype, s);
+    if (!e) return hipErrorInvalidValue;
+    return e->fn(g, w, T, scratch, stream, nullptr, rho_lo, rho_hi);
 }
 
 }  // namespace mwd

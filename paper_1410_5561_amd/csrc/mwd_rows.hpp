@@ -13,7 +13,7 @@ __global__ void __launch_bounds__(64 * DW * WPR)
 mwd_row_kernel(MwdArgs<T> a, MwdRow row)
 {
     using G = MwdGeom<K, DW, WPR>;
-    __shared__ T ex[2][G::L][G::NSX][G::LXP];
+    __shared__ T ex[2][G::L][G::NSX][G::LX];
     const int t = xcd_tile(blockIdx.x, gridDim.x, a.nxt);
     mwd_tile<K, T, DW, WPR>(a, row, t / a.nxt, t % a.nxt, ex);
 }
@@ -43,7 +43,7 @@ mwd_gather_kernel(MwdArgs<T> a)
 
 template <int K, typename T, int DW, int WPR>
 static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, void* const scratch[4],
-                           hipStream_t stream, Prof* prof)
+                           hipStream_t stream, Prof* prof, int rho_lo, int rho_hi)
 {
     using G = MwdGeom<K, DW, WPR>;
     MwdArgs<T> a{};
@@ -69,8 +69,13 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
     a.nsteps = nsteps;
     a.nxt = (g.nx + G::XT - 1) / G::XT;
     const int rho_max = (nsteps + G::H - 1) / G::H;
+    // rows [rho_lo, rho_hi] of the schedule; a partial range (the tuner's
+    // timing) skips the boundary fill and the gather
+    const bool whole = rho_lo <= 0 && rho_hi >= rho_max;
+    rho_lo = rho_lo < 0 ? 0 : rho_lo;
+    rho_hi = rho_hi > rho_max ? rho_max : rho_hi;
     // boundary values into the scratch pairs
-    {
+    if (whole) {
         HaloFill<T> hf;
         hf.src = a.halo;
         for (int k = 0; k < 4; ++k) hf.dst[k] = static_cast<T*>(scratch[k]);
@@ -87,7 +92,7 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    for (int rho = 0; rho <= rho_max; ++rho) {
+    for (int rho = rho_lo; rho <= rho_hi; ++rho) {
         MwdRow row;
         row.rho = rho;
         row.t0 = (rho - 1) * G::H;
@@ -100,6 +105,7 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (!whole) return hipSuccess;
     dim3 gg((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
     if (prof) prof->begin(stream);
     hipLaunchKernelGGL((mwd_gather_kernel<T, G::R, DW>), gg, dim3(256), 0, stream, a);
@@ -107,7 +113,7 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
     return hipGetLastError();
 }
 
-using RunFn = hipError_t (*)(const DevGrid&, const HostWeights&, int, void* const*, hipStream_t, Prof*);
+using RunFn = hipError_t (*)(const DevGrid&, const HostWeights&, int, void* const*, hipStream_t, Prof*, int, int);
 
 struct MwdEntry {
     int kind, dtype, dw, wpr;

@@ -60,7 +60,6 @@ struct MwdGeom {
     static constexpr int U = clcm(clcm(Q, WIN), PL);  // unroll: ring slots become constants
     static constexpr int NS = DW + 2 * R;           // LDS row slots (diamond rows + side rows)
     static constexpr int NSX = NS + 1;              // plus a spare row for writes nobody reads
-    static constexpr int LXP = LX + 2 * R;          // LDS row: the lanes plus R on each side
     static constexpr int S0 = U * ((R + PL + U - 1) / U);  // step offset, multiple of U, >= R + PL
 };
 
@@ -174,7 +173,7 @@ __global__ void __launch_bounds__(256) mwd_halo_fill_table_kernel(const HaloFill
 template <int K, typename T, int DW, int WPR>
 __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row, int b, int j,
                                          T (*ex)[MwdGeom<K, DW, WPR>::L][MwdGeom<K, DW, WPR>::NSX]
-                                              [MwdGeom<K, DW, WPR>::LXP])
+                                              [MwdGeom<K, DW, WPR>::LX])
 {
     using G = MwdGeom<K, DW, WPR>;
     constexpr int R = G::R, H = G::H, L = G::L, Q = G::Q, LX = G::LX, XT = G::XT;
@@ -329,48 +328,38 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             constexpr int tau = decltype(tc)::value;
             const int p = s - (tau + 1) * R;
             if (FAST || (((pmask >> tau) & 1u) && p >= 0 && p < a.nz))
-                ex[eb][tau][yr + R][xl + R] = q[tau][cmod(u - (tau + 1) * R, Q)];
+                ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
         });
         // side row: unconditional, so the wait for its load is the same on
         // every path
-        ex[eb][H - 1][side_slot][xl + R] = sv[k];
+        ex[eb][H - 1][side_slot][xl] = sv[k];
         __syncthreads();
         // (2) plane s - tau R of every level that is not computed here:
         //     boundary values, or the edge levels loaded PL steps ago (lanes
         //     that compute below overwrite theirs)
-        if constexpr (FAST) {
-            // uniform branches (kept as branches: no per-level lane masks)
-            static_for<0, L>([&](auto tc) {
-                constexpr int tau = decltype(tc)::value;
-                if (ea == tau) {
-                    keep_branch();
-                    q[tau][cmod(u - tau * R, Q)] = lea[k];
-                } else if (eb_ == tau) {
-                    keep_branch();
-                    q[tau][cmod(u - tau * R, Q)] = leb[k];
-                }
-            });
-            if (wave_bnd) {
-                static_for<0, L + 1>([&](auto tc) {
-                    constexpr int tau = decltype(tc)::value;
-                    T bv;
-                    if constexpr (tau == 0) bv = bzr[k];
-                    else bv = q[tau - 1][cmod(u - tau * R, Q)];
-                    if (!lane_in) q[tau][cmod(u - tau * R, Q)] = bv;
-                });
+        // edge levels: uniform branches (kept as branches, not lane selects)
+        static_for<0, L>([&](auto tc) {
+            constexpr int tau = decltype(tc)::value;
+            if (ea == tau) {
+                keep_branch();
+                q[tau][cmod(u - tau * R, Q)] = lea[k];
+            } else if (eb_ == tau) {
+                keep_branch();
+                q[tau][cmod(u - tau * R, Q)] = leb[k];
             }
-        } else {
+        });
+        // boundary values: lanes outside the domain, and, outside the steady
+        // state, every lane of a level whose plane is a boundary plane
+        const bool bnd_planes = !FAST && (s - L * R < 0 || s >= a.nz);
+        if (wave_bnd || bnd_planes) {
             static_for<0, L + 1>([&](auto tc) {
                 constexpr int tau = decltype(tc)::value;
                 const int p = s - tau * R;
-                const bool bnd = !lane_in || p < 0 || p >= a.nz;
-                T v = q[tau][cmod(u - tau * R, Q)];
-                if (has_a && ta == tau) v = lea[k];
-                if (has_b && tb == tau) v = leb[k];
+                const bool bnd = !lane_in || (!FAST && (p < 0 || p >= a.nz));
                 T bv;
                 if constexpr (tau == 0) bv = bzr[k];
                 else bv = q[tau - 1][cmod(u - tau * R, Q)];
-                q[tau][cmod(u - tau * R, Q)] = bnd ? bv : v;
+                if (bnd) q[tau][cmod(u - tau * R, Q)] = bv;
             });
         }
         // (3) stores of the previous step (its values are still in the
@@ -441,19 +430,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             }
         }
         // (5) advance every computed level by one plane, lowest level first:
-        //     level tau reads level tau - 1's plane p + R just made.  In the
-        //     steady state every lane computes (lanes outside the level's
-        //     range produce values nobody reads) and lanes outside the domain
-        //     then take the boundary value back.
+        //     level tau reads level tau - 1's plane p + R just made
         static_for<1, L + 1>([&](auto tc) {
             constexpr int tau = decltype(tc)::value;
             const int p = s - tau * R;
             if (((cmask >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
-                if (FAST || (xin && xl >= tau * R && xl < LX - tau * R)) {
+                if (xin && xl >= tau * R && xl < LX - tau * R) {
                     auto nb = [&](int dx, int dy, int dz) -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
-                        if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl + R];
-                        if (dx != 0) return ex[eb][tau - 1][yr + R][xl + R + dx];
+                        if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
+                        if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
                         return q[tau - 1][cmod(u - tau * R, Q)];
                     };
                     if constexpr (NARR > 0) {
@@ -464,9 +450,6 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                         q[tau][cmod(u - tau * R, Q)] =
                             apply_stencil<K, T>(nb, [&](int m) -> T { return a.w.c[m]; });
                     }
-                }
-                if constexpr (FAST) {
-                    if (wave_bnd && !lane_in) q[tau][cmod(u - tau * R, Q)] = q[tau - 1][cmod(u - tau * R, Q)];
                 }
             }
         });

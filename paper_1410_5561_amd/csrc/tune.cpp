@@ -1,16 +1,20 @@
 // Autotuner: choose between the naive sweep and the compiled MWD shapes
 // (diamond width, x lanes) by timing them on a proxy grid of the same x-y
-// extent, in the spirit of the paper's auto-tuning of diamond width, frontlines
-// and x-tile (Sec. II-A, Sec. IV-B).  The search space is pruned to shapes
-// whose tile kernel holds its working set in registers and LDS (a shape that
-// spills more than a few registers to scratch memory is not tried), the analogue of keeping the cache
-// block inside the cache (Sec. III-B).  Choices are cached per device and
-// size bucket for the life of the process and, if MWD_TUNE_CACHE names a
-// file, across processes.
+// extent, in the spirit of the paper's auto-tuning of diamond width,
+// frontlines and x-tile (Sec. II-A, Sec. IV-B).  The search space is pruned
+// to shapes whose tile kernel holds its working set in registers and LDS (a
+// shape that spills more than a few registers to scratch memory is not
+// tried), the analogue of keeping the cache block inside the cache
+// (Sec. III-B).  Each candidate's time for the whole run is predicted from a
+// few timed sweeps or diamond rows.  Choices are cached per device, stencil,
+// grid size and T for the life of the process and, if MWD_TUNE_CACHE names a
+// file, across processes.  MWD_TUNE_VERBOSE=1 prints every prediction to
+// stderr.
 #include "tune.hpp"
 
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -32,17 +36,19 @@ MwdShape default_shape(int kind, int dtype)
 
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int, int, int>;  // dev kind dtype nx ny nzp Tp batch
+using Key = std::tuple<int, int, int, int, int, int, int, int>;  // dev kind dtype nx ny nz T batch
 
 std::mutex g_mu;
 std::map<Key, TuneChoice> g_cache;
 bool g_file_loaded = false;
 
-constexpr int kProxyNz = 128;
+// The proxy grid holds at most this many bytes (its arrays: two levels, four
+// scratch arrays, the coefficient arrays) and at least this many planes.
+constexpr size_t kProxyBytes = size_t(32) << 30;
+constexpr int kMinProxyNz = 64;
 // A tile kernel that spills more than this to scratch memory (bytes per lane)
 // is not tried; a few spilled registers outside the step loop cost little.
 constexpr size_t kMaxSpillBytes = 32;
-constexpr int kProxyT = 32;
 
 const char* cache_path()
 {
@@ -151,8 +157,10 @@ bool make_proxy(Proxy& P, int kind, int dtype, int nx, int ny, int nz)
     return true;
 }
 
-// Milliseconds per run of T steps with the given choice, or a negative value.
-double time_choice(Proxy& P, int T, const TuneChoice& c, hipStream_t s)
+// Milliseconds of one call of f, averaged over three calls after a warm-up
+// call, or a negative value.
+template <class F>
+double time_ms(F&& f, hipStream_t s)
 {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.0;
@@ -160,37 +168,55 @@ double time_choice(Proxy& P, int T, const TuneChoice& c, hipStream_t s)
         (void)hipEventDestroy(e0);
         return -1.0;
     }
-    auto run = [&]() -> hipError_t {
-        if (c.mode == STENCIL_MODE_NAIVE) {
-            for (int t = 0; t < T; ++t) {
-                hipError_t e = naive_sweep(P.g, P.w, P.g.org[t & 1], P.g.org[(t + 1) & 1], s);
-                if (e != hipSuccess) return e;
-            }
-            return hipSuccess;
-        }
-        return mwd_run(P.g, P.w, T, c.shape, P.scratch, s, nullptr);
-    };
     double ms = -1.0;
-    hipError_t e = run();  // warm-up
+    hipError_t e = f();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = f();
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float f = 0.f;
-    if (e == hipSuccess && hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = f / 3.0;
+    float t = 0.f;
+    if (e == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 3.0;
     (void)hipGetLastError();
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return ms;
 }
 
+// Predicted milliseconds of a whole run of T steps over nz planes with the
+// given choice, from timing a part of it on the proxy (nzp planes): a few
+// sweeps of the naive schedule, or a few interior diamond rows of MWD (each
+// row costs about the same; the first and last rows are partial and count
+// as one row together).
+double predict_ms(Proxy& P, int T, int nz, const TuneChoice& c, hipStream_t s)
+{
+    const double zscale = (double)nz / (double)P.g.nz;
+    if (c.mode == STENCIL_MODE_NAIVE) {
+        const int ns = T < 4 ? (T > 0 ? T : 1) : 4;
+        const double ms = time_ms([&]() -> hipError_t {
+            for (int t = 0; t < ns; ++t) {
+                hipError_t e = naive_sweep(P.g, P.w, P.g.org[t & 1], P.g.org[(t + 1) & 1], s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }, s);
+        return ms < 0 ? ms : ms / ns * T * zscale;
+    }
+    const int h = c.shape.dw / (2 * radius_of(P.w.kind));
+    const int rho_max = (T + h - 1) / h;
+    if (rho_max <= 4) {
+        const double ms = time_ms([&]() { return mwd_run(P.g, P.w, T, c.shape, P.scratch, s, nullptr); }, s);
+        return ms < 0 ? ms : ms * zscale;
+    }
+    constexpr int kRows = 3;
+    const double ms = time_ms([&]() { return mwd_run_rows(P.g, P.w, T, c.shape, P.scratch, s, 1, kRows); }, s);
+    return ms < 0 ? ms : ms / kRows * rho_max * zscale;
+}
+
 int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch, TuneChoice* out)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return STENCIL_EDEVICE;
-    const int nzp = nz < kProxyNz ? nz : kProxyNz;
-    const int Tp = T < kProxyT ? (T > 0 ? T : 1) : kProxyT;
-    const Key key{dev, kind, dtype, nx, ny, nzp, Tp, batch ? 1 : 0};
+    const Key key{dev, kind, dtype, nx, ny, nz, T, batch ? 1 : 0};
     std::lock_guard<std::mutex> lk(g_mu);
     load_file();
     auto it = g_cache.find(key);
@@ -220,6 +246,13 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch,
     const char* ve = std::getenv("MWD_TUNE_VERBOSE");
     const bool verbose = ve && *ve && *ve != '0';
     if (cands.size() > 1) {
+        // proxy: the same x-y extent, and as many planes as fit the budget
+        const int h = radius_of(kind);
+        const size_t es = dtype == 0 ? 8 : 4;
+        const size_t plane = (size_t)(nx + 2 * h) * (size_t)(ny + 2 * h) * es;
+        const size_t arrays = 6 + (size_t)narr_of(kind);
+        const long long fit = (long long)(kProxyBytes / (arrays * plane)) - 2 * h;
+        const int nzp = (int)std::max<long long>(std::min<long long>(nz, kMinProxyNz), std::min<long long>(nz, fit));
         Proxy P;
         hipStream_t s = nullptr;
         double best_ms = -1.0;
@@ -227,10 +260,10 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch,
             for (const TuneChoice& c : cands) {
                 // a batched shape is timed through the row kernel of the same tile
                 if (c.mode == STENCIL_MODE_MWD && !mwd_supported(kind, dtype, c.shape)) continue;
-                const double ms = time_choice(P, Tp, c, s);
+                const double ms = predict_ms(P, T, nz, c, s);
                 if (verbose)
-                    std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d T=%d%s: %s dw %d lanes %d: %.3f ms\n",
-                                 kind, dtype, nx, ny, nzp, Tp, batch ? " (batched)" : "",
+                    std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d (proxy %d planes) T=%d%s: %s dw %d lanes %d: %.3f ms\n",
+                                 kind, dtype, nx, ny, nz, nzp, T, batch ? " (batched)" : "",
                                  c.mode == STENCIL_MODE_NAIVE ? "naive" : "mwd", c.shape.dw, c.shape.wpr * 64, ms);
                 if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
                     best_ms = ms;
