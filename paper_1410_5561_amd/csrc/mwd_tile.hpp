@@ -320,6 +320,13 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         constexpr bool FAST = decltype(fc)::value;
         constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
         const int eb = s & 1;
+        // the wave's level sets, re-read at every step so that the per-level
+        // tests below stay scalar compares instead of lane masks held (and
+        // spilled) across the loop
+        const uint32_t cm = (uint32_t)opaque_uniform((int)cmask);
+        const uint32_t pm = (uint32_t)opaque_uniform((int)pmask);
+        const uint32_t sm = (uint32_t)opaque_uniform((int)smask);
+        const int e1 = opaque_uniform(ea), e2 = opaque_uniform(eb_);
         // (1) publish, for every level tau < L, the plane level tau + 1 reads
         //     in-plane neighbours from at this step, and the side row.  In the
         //     steady state a level this row does not hold publishes too: no
@@ -327,7 +334,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         static_for<0, L>([&](auto tc) {
             constexpr int tau = decltype(tc)::value;
             const int p = s - (tau + 1) * R;
-            if (FAST || (((pmask >> tau) & 1u) && p >= 0 && p < a.nz))
+            if (FAST || (((pm >> tau) & 1u) && p >= 0 && p < a.nz))
                 ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
         });
         // side row: unconditional, so the wait for its load is the same on
@@ -340,10 +347,10 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         // edge levels: uniform branches (kept as branches, not lane selects)
         static_for<0, L>([&](auto tc) {
             constexpr int tau = decltype(tc)::value;
-            if (ea == tau) {
+            if (e1 == tau) {
                 keep_branch();
                 q[tau][cmod(u - tau * R, Q)] = lea[k];
-            } else if (eb_ == tau) {
+            } else if (e2 == tau) {
                 keep_branch();
                 q[tau][cmod(u - tau * R, Q)] = leb[k];
             }
@@ -371,13 +378,13 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             if constexpr (FAST) {
                 // cb[4 + (tau & 1)]: corner of plane sb - 1 - LR of the
                 // buffer that holds level tau
-                if (((smask >> tau) & 1u) && xout) {
+                if (((sm >> tau) & 1u) && xout) {
                     char* base = const_cast<char*>(cb[4 + (tau & 1)]);
                     const uint32_t off = colb + opaque_u32((uint32_t)((u + (L - tau) * R) * szb));
                     *reinterpret_cast<T*>(base + off) = q[tau][cmod(u - 1 - tau * R, Q)];
                 }
             } else {
-                if (((smask >> tau) & 1u) && p >= 0 && p < a.nz && xout)
+                if (((sm >> tau) & 1u) && p >= 0 && p < a.nz && xout)
                     *reinterpret_cast<T*>(const_cast<char*>(plane(dst[tau], p)) + colb) =
                         q[tau][cmod(u - 1 - tau * R, Q)];
             }
@@ -399,7 +406,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             if (wave_bnd) bzr[k] = ld(cb[3], o);
             if constexpr (NARR > 0) {
                 constexpr int PD = G::PD;
-                if (cmask != 0u) {
+                if (cm != 0u) {
 #pragma unroll
                     for (int m = 0; m < NARR; ++m) cr[m][cmod(u + PD - R, WIN)] = ld(cb[6 + m], o);
                 }
@@ -418,11 +425,11 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             // boundary values: at boundary planes every lane needs them, at
             // other planes the lanes outside the domain
             const bool pbnd = pl < 0 || pl >= a.nz;
-            if (pmask != 0u && (wave_bnd || pbnd)) bzr[k] = gld(a.halo, pl, -R, a.nz + R, colb);
+            if (pm != 0u && (wave_bnd || pbnd)) bzr[k] = gld(a.halo, pl, -R, a.nz + R, colb);
             if constexpr (NARR > 0) {
                 constexpr int PD = G::PD;
                 const int pc = s + PD - R;
-                if (cmask != 0u) {
+                if (cm != 0u) {
 #pragma unroll
                     for (int m = 0; m < NARR; ++m)
                         cr[m][cmod(u + PD - R, WIN)] = gld(a.w.arr[m], pc, 0, a.nz, colb);
@@ -434,7 +441,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         static_for<1, L + 1>([&](auto tc) {
             constexpr int tau = decltype(tc)::value;
             const int p = s - tau * R;
-            if (((cmask >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
+            if (((cm >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
                 if (xin && xl >= tau * R && xl < LX - tau * R) {
                     auto nb = [&](int dx, int dy, int dz) -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
