@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "batch_naive.hpp"
 #include "batch_variants.hpp"
 #include "internal.hpp"
 #include "tune.hpp"
@@ -90,11 +91,16 @@ template <typename T>
 static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* hw, int n, int T_steps,
                        int dtype, std::string* errmsg)
 {
-    // 1. shape per grid (autotuned per kind and size bucket)
+    // 1. schedule per grid (autotuned per kind and size bucket): the batched
+    //    naive sweep (var -1) or a batched MWD shape
     std::vector<int> var(n);
     for (int i = 0; i < n; ++i) {
-        MwdShape s = tune_batch_shape(hw[i].kind, dtype, grids[i].nx, grids[i].ny, grids[i].nz, T_steps);
-        int v = variant_index(hw[i].kind, dtype, s);
+        const TuneChoice c = tune_batch_choose(hw[i].kind, dtype, grids[i].nx, grids[i].ny, grids[i].nz, T_steps);
+        if (c.mode == STENCIL_MODE_NAIVE) {
+            var[i] = -1;
+            continue;
+        }
+        int v = variant_index(hw[i].kind, dtype, c.shape);
         if (v < 0) {
             *errmsg = "no batched tile shape for kind " + std::to_string(hw[i].kind);
             return STENCIL_EUNSUPPORTED;
@@ -106,7 +112,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     for (int i = 0; i < n; ++i) {
         const size_t bytes = (size_t)grids[i].sz * (size_t)(grids[i].nz + 2 * grids[i].halo) * es_of(dtype);
         const size_t aligned = (bytes + 255) & ~size_t(255);
-        soff[i + 1] = soff[i] + 4 * aligned;
+        soff[i + 1] = soff[i] + (var[i] >= 0 ? 4 * aligned : 0);
     }
     if (hipMalloc(&bg.scratch, soff[n] ? soff[n] : 256) != hipSuccess) {
         (void)hipGetLastError();
@@ -121,12 +127,41 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     std::vector<BatchTile> tiles;
     std::vector<int> rows(n), nxt(n);
     int max_rows = 0;
+    std::vector<NaiveArgs<T>> nargs(n);
+    std::vector<NaiveTile> ntiles;
     for (int i = 0; i < n; ++i) {
+        DevGrid d = to_dev(&grids[i]);
+        if (var[i] < 0) {
+            // naive: (x block, y block, z chunk) entries of this grid
+            NaiveArgs<T>& na = nargs[i];
+            std::memset(&na, 0, sizeof(na));
+            na.buf[0] = static_cast<T*>(d.org[0]);
+            na.buf[1] = static_cast<T*>(d.org[1]);
+            for (int m = 0; m < 13; ++m) {
+                na.w.c[m] = static_cast<T>(hw[i].c[m]);
+                na.w.arr[m] = static_cast<const T*>(hw[i].org[m]);
+            }
+            na.kind = hw[i].kind;
+            na.nx = d.nx;
+            na.ny = d.ny;
+            na.nz = d.nz;
+            na.zchunk = 64;
+            na.cur = d.cur;
+            na.sy = d.sy;
+            na.sz = d.sz;
+            for (int bz = 0; bz * na.zchunk < d.nz; ++bz)
+                for (int by = 0; by * kNaiveBY < d.ny; ++by)
+                    for (int bx = 0; bx * kNaiveBX < d.nx; ++bx) ntiles.push_back(NaiveTile{i, bx, by, bz});
+            std::memset(&gargs[i], 0, sizeof(gargs[i]));
+            std::memset(&halo[i], 0, sizeof(halo[i]));  // nx = 0: the fill skips it
+            rows[i] = 0;
+            nxt[i] = 0;
+            continue;
+        }
         const BatchVariantInfo& vi = kBatchVariantInfo[var[i]];
         const MwdShape s{vi.dw, vi.wpr};
         const int R = radius_of(vi.kind), H = vi.dw / (2 * R);
         const int XT = mwd_xtile(vi.kind, s);
-        DevGrid d = to_dev(&grids[i]);
         const size_t es = es_of(dtype);
         const size_t bytes = (soff[i + 1] - soff[i]) / 4;
         const long long off = (long long)d.halo * d.sz + (long long)d.halo * d.sy + d.halo;
@@ -180,6 +215,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     // the gather of every grid's last two levels
     group_first.push_back((int)tiles.size());
     for (int i = 0; i < n; ++i) {
+        if (var[i] < 0) continue;
         const int zc = std::max(1, (int)(65536 / std::max(1LL, (long long)grids[i].nx * grids[i].ny)));
         for (int z0 = 0; z0 < grids[i].nz; z0 += zc)
             tiles.push_back(BatchTile{i, 1, -1, 0, 0, z0, std::min(zc, grids[i].nz - z0), 0});
@@ -190,8 +226,10 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     const size_t ab = (size_t)n * sizeof(MwdArgs<T>);
     const size_t vb = (size_t)n * sizeof(int);
     const size_t hb = (size_t)n * sizeof(HaloFill<T>);
+    const size_t ntb = ntiles.size() * sizeof(NaiveTile);
+    const size_t nab = (size_t)n * sizeof(NaiveArgs<T>);
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    if (hipMalloc(&bg.dev, al(tb) + al(ab) + al(vb) + al(hb)) != hipSuccess) {
+    if (hipMalloc(&bg.dev, al(tb) + al(ab) + al(vb) + al(hb) + al(ntb) + al(nab)) != hipSuccess) {
         (void)hipGetLastError();
         bg.dev = nullptr;
         *errmsg = "batched table allocation failed";
@@ -202,10 +240,14 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     MwdArgs<T>* d_args = reinterpret_cast<MwdArgs<T>*>(base + al(tb));
     int* d_var = reinterpret_cast<int*>(base + al(tb) + al(ab));
     HaloFill<T>* d_halo = reinterpret_cast<HaloFill<T>*>(base + al(tb) + al(ab) + al(vb));
+    NaiveTile* d_ntiles = reinterpret_cast<NaiveTile*>(base + al(tb) + al(ab) + al(vb) + al(hb));
+    NaiveArgs<T>* d_nargs = reinterpret_cast<NaiveArgs<T>*>(base + al(tb) + al(ab) + al(vb) + al(hb) + al(ntb));
     hipError_t e = hipMemcpy(d_tiles, tiles.data(), tb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_args, gargs.data(), ab, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_var, var.data(), vb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_halo, halo.data(), hb, hipMemcpyHostToDevice);
+    if (e == hipSuccess && ntb) e = hipMemcpy(d_ntiles, ntiles.data(), ntb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_nargs, nargs.data(), nab, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         *errmsg = std::string("batched table upload: ") + hipGetErrorString(e);
         return STENCIL_EDEVICE;
@@ -225,6 +267,12 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         const dim3 hgrid(hgx, hgy, n);
         hipError_t el = sizeof(T) == 8 ? batch_halo_launch_f64(reinterpret_cast<const HaloFill<double>*>(d_halo), hgrid, cs)
                                        : batch_halo_launch_f32(reinterpret_cast<const HaloFill<float>*>(d_halo), hgrid, cs);
+        // the naive grids: one launch per time step, all grids together
+        for (int t = 0; t < T_steps && !ntiles.empty() && el == hipSuccess; ++t) {
+            NaiveLaunch<T> NL{d_ntiles, d_nargs, t};
+            if constexpr (sizeof(T) == 8) el = batch_naive_launch_f64(NL, (int)ntiles.size(), cs);
+            else el = batch_naive_launch_f32(NL, (int)ntiles.size(), cs);
+        }
         for (size_t g = 0; g + 1 < group_first.size() && el == hipSuccess; ++g) {
             const int cnt = group_first[g + 1] - group_first[g];
             if (cnt <= 0) continue;

@@ -24,6 +24,10 @@ template <> struct KindTraits<K7V>  { static constexpr int R = 1, NARR = 7,  NW 
 template <> struct KindTraits<K25C> { static constexpr int R = 4, NARR = 0,  NW = 13, ND = 2;  };
 template <> struct KindTraits<K25V> { static constexpr int R = 4, NARR = 13, NW = 13, ND = 15; };
 
+// Lambdas of the hot loops are always inlined: a step body that is not would
+// keep its register queues in scratch memory.
+#define MWD_INLINE __attribute__((always_inline))
+
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -67,7 +71,7 @@ __device__ __forceinline__ T apply_stencil(const NB& nb, const WF& w) {
         return u;
     } else {
         T u = w(0) * nb(0, 0, 0);
-        static_for<1, 5>([&](auto rc) {
+        static_for<1, 5>([&](auto rc) MWD_INLINE {
             constexpr int r = decltype(rc)::value;
             u = u + w(3 * (r - 1) + 1) * (nb(r, 0, 0) + nb(-r, 0, 0));
             u = u + w(3 * (r - 1) + 2) * (nb(0, r, 0) + nb(0, -r, 0));

@@ -49,8 +49,9 @@ struct MwdGeom {
     static_assert(NT <= 1024, "workgroup too large");
     static constexpr int Q = 2 * R + 1;             // z-queue length per level
     // Loads are issued PL steps before the step that consumes them, so that
-    // PL steps of compute cover the memory latency.
-    static constexpr int PL = 3;
+    // PL steps of compute cover the memory latency (two for the radius-4
+    // stencil, whose 9-plane queues leave fewer registers).
+    static constexpr int PL = R == 1 ? 3 : 2;
     // coefficient ring: planes [s - LR, s - R] are in use at step s, and the
     // load for plane s + PD - R is in flight; the ring is rounded up to a
     // multiple of Q and PD takes what the rounding leaves (at least 2)
@@ -197,7 +198,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
 
     // Is level tau of diamond row yrr computed by this tile (clipped to the
     // domain and to 1 <= t <= T)?  Wave-uniform.
-    auto computed = [&](int yrr, int tau) -> bool {
+    auto computed = [&](int yrr, int tau) MWD_INLINE -> bool {
         if (tau < 1 || tau > L || yrr < 0 || yrr >= DW) return false;
         const int t = row.t0 + tau;
         if (t < 1 || t > a.nsteps) return false;
@@ -206,14 +207,14 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         const int d = yrr < DW / 2 ? DW / 2 - 1 - yrr : yrr - DW / 2;
         return d < R * min(tau, 2 * H - tau);
     };
-    auto needed = [&](int yrr, int tau) -> bool {
+    auto needed = [&](int yrr, int tau) MWD_INLINE -> bool {
         if (tau >= L) return false;
         bool n = false;
         for (int dy = -R; dy <= R; ++dy) n = n || computed(yrr + dy, tau + 1);
         return n;
     };
     // Source of a level-t value at row yy that this tile does not compute.
-    auto level_src = [&](int yy, int t) -> const T* {
+    auto level_src = [&](int yy, int t) MWD_INLINE -> const T* {
         if (t < 0 || yy < 0 || yy >= a.ny) return a.halo;
         const int p = (t == 0) ? 0 : pair_of_row(row_of<R, DW>(yy, t));
         return a.pair[p][(a.cur + t) & 1];
@@ -266,11 +267,14 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     const T* sv_src = level_src(sv_y, row.t0 + H - 1);
     const int side_slot = sv_present ? yrs + R : G::NS;  // NS: the spare row
 
-    T q[L + 1][Q];
+    // z-queues of levels 0 .. L-1; the top level L is read by no other level,
+    // only by the delayed stores, so it keeps just its current and previous plane
+    T q[L][Q];
+    T qtop = T(0), qtop_prev = T(0);
     T lea[PL], leb[PL], bzr[PL], sv[PL];
     T cr[NARR > 0 ? NARR : 1][WIN];
 #pragma unroll
-    for (int tau = 0; tau <= L; ++tau)
+    for (int tau = 0; tau < L; ++tau)
 #pragma unroll
         for (int k = 0; k < Q; ++k) q[tau][k] = T(0);
 #pragma unroll
@@ -307,15 +311,15 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                                ? (uint32_t)(((long long)(sv_y + R) * a.sy + x + R) * (long long)sizeof(T))
                                : 0u;
     // byte address of the corner of plane p of an array
-    auto plane = [&](const T* arr, int p) -> const char* {
+    auto plane = [&](const T* arr, int p) MWD_INLINE -> const char* {
         return reinterpret_cast<const char*>(arr) + ((long long)p * a.sz - corner) * (long long)sizeof(T);
     };
-    auto ld = [](const char* base, uint32_t off) -> T { return *reinterpret_cast<const T*>(base + off); };
+    auto ld = [](const char* base, uint32_t off) MWD_INLINE -> T { return *reinterpret_cast<const T*>(base + off); };
     const int par0 = (a.cur + row.t0) & 1;  // buffer of the even levels
     const int ea = has_a ? ta : -1, eb_ = has_b ? tb : -1;  // edge levels, -1: none
 
     // One wavefront step.  FAST: a steady-state step (see above).
-    auto step = [&](auto uc, auto fc, int s, const char* const* cb) {
+    auto step = [&](auto uc, auto fc, int s, const char* const* cb) MWD_INLINE {
         constexpr int u = decltype(uc)::value;
         constexpr bool FAST = decltype(fc)::value;
         constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
@@ -327,11 +331,18 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         const uint32_t pm = (uint32_t)opaque_uniform((int)pmask);
         const uint32_t sm = (uint32_t)opaque_uniform((int)smask);
         const int e1 = opaque_uniform(ea), e2 = opaque_uniform(eb_);
+        qtop_prev = qtop;  // level L's plane s - 1 - LR, for this step's stores
+        // plane s - 1 - tau R of level tau (the previous step's), for the stores
+        auto qold = [&](auto tc) MWD_INLINE -> T {
+            constexpr int tau = decltype(tc)::value;
+            if constexpr (tau == L) return qtop_prev;
+            else return q[tau][cmod(u - 1 - tau * R, Q)];
+        };
         // (1) publish, for every level tau < L, the plane level tau + 1 reads
         //     in-plane neighbours from at this step, and the side row.  In the
         //     steady state a level this row does not hold publishes too: no
         //     other row reads that slot.
-        static_for<0, L>([&](auto tc) {
+        static_for<0, L>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             const int p = s - (tau + 1) * R;
             if (FAST || (((pm >> tau) & 1u) && p >= 0 && p < a.nz))
@@ -345,7 +356,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         //     boundary values, or the edge levels loaded PL steps ago (lanes
         //     that compute below overwrite theirs)
         // edge levels: uniform branches (kept as branches, not lane selects)
-        static_for<0, L>([&](auto tc) {
+        static_for<0, L>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             if (e1 == tau) {
                 keep_branch();
@@ -359,20 +370,24 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         // state, every lane of a level whose plane is a boundary plane
         const bool bnd_planes = !FAST && (s - L * R < 0 || s >= a.nz);
         if (wave_bnd || bnd_planes) {
-            static_for<0, L + 1>([&](auto tc) {
+            static_for<0, L + 1>([&](auto tc) MWD_INLINE {
                 constexpr int tau = decltype(tc)::value;
                 const int p = s - tau * R;
                 const bool bnd = !lane_in || (!FAST && (p < 0 || p >= a.nz));
                 T bv;
                 if constexpr (tau == 0) bv = bzr[k];
                 else bv = q[tau - 1][cmod(u - tau * R, Q)];
-                if (bnd) q[tau][cmod(u - tau * R, Q)] = bv;
+                if constexpr (tau == L) {
+                    if (bnd) qtop = bv;
+                } else {
+                    if (bnd) q[tau][cmod(u - tau * R, Q)] = bv;
+                }
             });
         }
         // (3) stores of the previous step (its values are still in the
         //     queues): the last two levels of each point.  Issued before this
         //     step's loads, so waits on those loads stay exact.
-        static_for<1, L + 1>([&](auto tc) {
+        static_for<1, L + 1>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             const int p = s - 1 - tau * R;
             if constexpr (FAST) {
@@ -381,12 +396,11 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 if (((sm >> tau) & 1u) && xout) {
                     char* base = const_cast<char*>(cb[4 + (tau & 1)]);
                     const uint32_t off = colb + opaque_u32((uint32_t)((u + (L - tau) * R) * szb));
-                    *reinterpret_cast<T*>(base + off) = q[tau][cmod(u - 1 - tau * R, Q)];
+                    *reinterpret_cast<T*>(base + off) = qold(tc);
                 }
             } else {
                 if (((sm >> tau) & 1u) && p >= 0 && p < a.nz && xout)
-                    *reinterpret_cast<T*>(const_cast<char*>(plane(dst[tau], p)) + colb) =
-                        q[tau][cmod(u - 1 - tau * R, Q)];
+                    *reinterpret_cast<T*>(const_cast<char*>(plane(dst[tau], p)) + colb) = qold(tc);
             }
         });
         // (4) issue the loads consumed PL steps from now (PD for the
@@ -414,7 +428,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         } else {
             // a stream whose plane lies outside its range loads, on every
             // lane, the corner of the nearest plane inside it
-            auto gld = [&](const T* arr, int p, int lo, int hi, uint32_t off) -> T {
+            auto gld = [&](const T* arr, int p, int lo, int hi, uint32_t off) MWD_INLINE -> T {
                 const bool in = p >= lo && p < hi;
                 return ld(plane(arr, min(max(p, lo), hi - 1)), in ? off : 0u);
             };
@@ -438,34 +452,34 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         }
         // (5) advance every computed level by one plane, lowest level first:
         //     level tau reads level tau - 1's plane p + R just made
-        static_for<1, L + 1>([&](auto tc) {
+        static_for<1, L + 1>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             const int p = s - tau * R;
             if (((cm >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
                 if (xin && xl >= tau * R && xl < LX - tau * R) {
-                    auto nb = [&](int dx, int dy, int dz) -> T {
+                    auto nb = [&](int dx, int dy, int dz) MWD_INLINE -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
                         if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
                         if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
                         return q[tau - 1][cmod(u - tau * R, Q)];
                     };
+                    T v;
                     if constexpr (NARR > 0) {
-                        q[tau][cmod(u - tau * R, Q)] = apply_stencil<K, T>(nb, [&](int m) -> T {
-                            return cr[m][cmod(u - tau * R, WIN)];
-                        });
+                        v = apply_stencil<K, T>(nb, [&](int m) MWD_INLINE -> T { return cr[m][cmod(u - tau * R, WIN)]; });
                     } else {
-                        q[tau][cmod(u - tau * R, Q)] =
-                            apply_stencil<K, T>(nb, [&](int m) -> T { return a.w.c[m]; });
+                        v = apply_stencil<K, T>(nb, [&](int m) MWD_INLINE -> T { return a.w.c[m]; });
                     }
+                    if constexpr (tau == L) qtop = v;
+                    else q[tau][cmod(u - tau * R, Q)] = v;
                 }
             }
         });
     };
 
     const char* const nocb[1] = {nullptr};
-    auto generic_chunks = [&](int from, int to) {
+    auto generic_chunks = [&](int from, int to) MWD_INLINE {
         for (int sb = from; sb < to; sb += U)
-            static_for<0, U>([&](auto uc) {
+            static_for<0, U>([&](auto uc) MWD_INLINE {
                 step(uc, std::false_type{}, opaque_uniform(sb + decltype(uc)::value), nocb);
             });
     };
@@ -483,7 +497,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
 #pragma unroll
             for (int m = 0; m < NARR; ++m) cb[6 + m] = plane(a.w.arr[m], sb + G::PD - R);
         }
-        static_for<0, U>([&](auto uc) { step(uc, std::true_type{}, sb + decltype(uc)::value, cb); });
+        static_for<0, U>([&](auto uc) MWD_INLINE { step(uc, std::true_type{}, sb + decltype(uc)::value, cb); });
     }
     generic_chunks(s_fast_end, s_last + 1);
 }

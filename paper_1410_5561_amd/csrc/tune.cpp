@@ -48,7 +48,7 @@ constexpr size_t kProxyBytes = size_t(32) << 30;
 constexpr int kMinProxyNz = 64;
 // A tile kernel that spills more than this to scratch memory (bytes per lane)
 // is not tried; a few spilled registers outside the step loop cost little.
-constexpr size_t kMaxSpillBytes = 32;
+constexpr size_t kMaxSpillBytes = 128;
 
 const char* cache_path()
 {
@@ -212,11 +212,11 @@ double predict_ms(Proxy& P, int T, int nz, const TuneChoice& c, hipStream_t s)
     return ms < 0 ? ms : ms / kRows * rho_max * zscale;
 }
 
-int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch, TuneChoice* out)
+int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, int batch, TuneChoice* out)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return STENCIL_EDEVICE;
-    const Key key{dev, kind, dtype, nx, ny, nz, T, batch ? 1 : 0};
+    const Key key{dev, kind, dtype, nx, ny, nz, T, batch};
     std::lock_guard<std::mutex> lk(g_mu);
     load_file();
     auto it = g_cache.find(key);
@@ -227,6 +227,8 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch,
     // candidates
     std::vector<TuneChoice> cands;
     if (batch) {
+        // batch 1: the batched naive sweep or a batched MWD shape; 2: MWD only
+        if (batch == 1) cands.push_back(TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}});
         const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
         for (int i = 0; i < nv; ++i)
             if (kBatchVariantInfo[i].kind == kind)
@@ -285,23 +287,26 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, bool batch,
 int tune_choose(int kind, int dtype, int nx, int ny, int nz, int T, TuneChoice* out)
 {
     if (forced(kind, dtype, out)) return STENCIL_OK;
-    return tune_generic(kind, dtype, nx, ny, nz, T, false, out);
+    return tune_generic(kind, dtype, nx, ny, nz, T, 0, out);
 }
 
-MwdShape tune_batch_shape(int kind, int dtype, int nx, int ny, int nz, int T)
+TuneChoice tune_batch_choose(int kind, int dtype, int nx, int ny, int nz, int T)
 {
+    const char* e = std::getenv("MWD_TUNE");
+    if (e && std::strcmp(e, "naive") == 0) return TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}};
+    const bool mwd_only = e && std::strncmp(e, "mwd", 3) == 0;
     // bucket the extents so that a batch of many uneven grids tunes a few
     // representative sizes
     auto bucket = [](int n) { return n <= 64 ? 64 : n <= 128 ? 128 : 256; };
     TuneChoice c;
-    if (tune_generic(kind, dtype, bucket(nx), bucket(ny), bucket(nz), T, true, &c) == STENCIL_OK &&
-        c.mode == STENCIL_MODE_MWD)
-        return c.shape;
+    if (tune_generic(kind, dtype, bucket(nx), bucket(ny), bucket(nz), T, mwd_only ? 2 : 1, &c) == STENCIL_OK)
+        return c;
     // the first compiled variant of this kind
     const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
     for (int i = 0; i < nv; ++i)
-        if (kBatchVariantInfo[i].kind == kind) return MwdShape{kBatchVariantInfo[i].dw, kBatchVariantInfo[i].wpr};
-    return MwdShape{0, 0};
+        if (kBatchVariantInfo[i].kind == kind)
+            return TuneChoice{STENCIL_MODE_MWD, MwdShape{kBatchVariantInfo[i].dw, kBatchVariantInfo[i].wpr}};
+    return TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}};
 }
 
 }  // namespace mwd

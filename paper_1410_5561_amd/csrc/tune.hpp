@@ -17,8 +17,10 @@ MwdShape default_shape(int kind, int dtype);
 // Returns a STENCIL_* code.
 int tune_choose(int kind, int dtype, int nx, int ny, int nz, int T, TuneChoice* out);
 
-// Tile shape of one grid inside the batched kernel (one of the shapes compiled
-// into it, all sized for 1024-thread workgroups).
-MwdShape tune_batch_shape(int kind, int dtype, int nx, int ny, int nz, int T);
+// Schedule of one grid inside a batch: the batched naive sweep, or one of the
+// MWD tile shapes compiled into the batched kernel (all sized for 1024-thread
+// workgroups).  MWD_TUNE=naive forces the naive sweep, MWD_TUNE=mwd (or
+// mwd:<dw>:<lanes>) the best batched MWD shape.
+TuneChoice tune_batch_choose(int kind, int dtype, int nx, int ny, int nz, int T);
 
 }  // namespace mwd

@@ -1,4 +1,5 @@
-"""GPU: the batched persistent form and the FP64 reductions, through the C ABI,
+"""GPU: the batched form (one hipGraph: batched naive sweeps for some grids,
+MWD row groups for others) and the FP64 reductions, through the C ABI,
 against the CPU oracle."""
 from __future__ import annotations
 
@@ -15,22 +16,32 @@ pytestmark = pytest.mark.gpu
 
 SPECS = [("7c", (40, 33, 20)), ("25c", (50, 37, 18)), ("7c", (17, 70, 9)), ("25c", (33, 16, 40)),
          ("7c", (130, 5, 7)), ("25c", (64, 64, 11)), ("7c", (3, 2, 1)), ("25c", (1, 9, 30)),
-         ("7c", (96, 48, 32))]
+         ("7c", (96, 48, 32)), ("7v", (45, 20, 13))]
 
 
 def _inputs(kind, n, dtype, seed):
     R = gridgen.RADIUS[kind]
     u0 = gridgen.field(seed, *n, R, -1.0, 1.0, dtype)
-    co = gridgen.C7 if kind == "7c" else gridgen.C25
+    if kind == "7v":
+        co = [c.astype(dtype) for c in gridgen.coeffs_7v(seed, *n, R)]
+    else:
+        co = gridgen.C7 if kind == "7c" else gridgen.C25
     return u0, co
 
 
 @pytest.mark.parametrize("dts", ["f32", "f64"])
 @pytest.mark.parametrize("T", [16, 5])
-def test_batched_mixed_grids_bitexact_and_replay(dts, T):
+@pytest.mark.parametrize("sched", ["auto", "naive", "mwd"])
+def test_batched_mixed_grids_bitexact_and_replay(dts, T, sched, monkeypatch):
+    """Every grid of a mixed batch matches the oracle bit for bit after each
+    of three replays of the same graph, with the schedule the tuner picks per
+    grid, and with every grid forced onto the batched naive sweep or onto the
+    batched MWD tiles (kinds without a batched tile shape stay naive)."""
     import torch
+    if sched != "auto":
+        monkeypatch.setenv("MWD_TUNE", sched)
     dtype = np.float64 if dts == "f64" else np.float32
-    print("batched", dts, "T", T, flush=True)
+    print("batched", dts, "T", T, sched, flush=True)
     inputs = [_inputs(k, n, dtype, 100 + i) for i, (k, n) in enumerate(SPECS)]
     grids, keep, coeffs = [], [], []
     for (kind, n), (u0, co) in zip(SPECS, inputs):
