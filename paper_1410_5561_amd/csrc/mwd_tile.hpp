@@ -452,6 +452,23 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         }
         // (5) advance every computed level by one plane, lowest level first:
         //     level tau reads level tau - 1's plane p + R just made
+        //     Where registers allow (radius 1 with at most 3 levels, or 7 in
+        //     FP32), the in-plane neighbours of every level are read from
+        //     LDS up front, so that the levels' chain does not wait on LDS
+        //     once per level.
+        constexpr bool XYPF = R == 1 && (L <= 3 || (sizeof(T) == 4 && L <= 7));
+        T xy[XYPF ? L + 1 : 1][4];
+        if constexpr (XYPF) {
+            if (xl >= R && xl < LX - R) {
+                static_for<1, L + 1>([&](auto tc) MWD_INLINE {
+                    constexpr int tau = decltype(tc)::value;
+                    xy[tau][0] = ex[eb][tau - 1][yr + R][xl + 1];
+                    xy[tau][1] = ex[eb][tau - 1][yr + R][xl - 1];
+                    xy[tau][2] = ex[eb][tau - 1][yr + R + 1][xl];
+                    xy[tau][3] = ex[eb][tau - 1][yr + R - 1][xl];
+                });
+            }
+        }
         static_for<1, L + 1>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             const int p = s - tau * R;
@@ -459,8 +476,15 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 if (xin && xl >= tau * R && xl < LX - tau * R) {
                     auto nb = [&](int dx, int dy, int dz) MWD_INLINE -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
-                        if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
-                        if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
+                        if constexpr (XYPF) {
+                            if (dx > 0) return xy[tau][0];
+                            if (dx < 0) return xy[tau][1];
+                            if (dy > 0) return xy[tau][2];
+                            if (dy < 0) return xy[tau][3];
+                        } else {
+                            if (dy != 0) return ex[eb][tau - 1][yr + R + dy][xl];
+                            if (dx != 0) return ex[eb][tau - 1][yr + R][xl + dx];
+                        }
                         return q[tau - 1][cmod(u - tau * R, Q)];
                     };
                     T v;
