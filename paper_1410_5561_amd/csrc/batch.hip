@@ -53,6 +53,10 @@ static size_t es_of(int dtype) { return dtype == 0 ? 8 : 4; }
 
 // run of adjacent tiles given to one XCD in a batched row group
 constexpr int kBatchXcdRun = 4;
+// arrays of one group of naive grids: within the 256 MiB last-level cache
+constexpr size_t kCacheGroupBytes = size_t(160) << 20;
+// workgroups per launch below which a group's z chunks are halved
+constexpr long long kNaiveMinBlocks = 2048;
 
 static int variant_index(int kind, int dtype, const MwdShape& s)
 {
@@ -145,13 +149,10 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
             na.nx = d.nx;
             na.ny = d.ny;
             na.nz = d.nz;
-            na.zchunk = 64;
+            na.zchunk = 64;  // set per group below
             na.cur = d.cur;
             na.sy = d.sy;
             na.sz = d.sz;
-            for (int bz = 0; bz * na.zchunk < d.nz; ++bz)
-                for (int by = 0; by * kNaiveBY < d.ny; ++by)
-                    for (int bx = 0; bx * kNaiveBX < d.nx; ++bx) ntiles.push_back(NaiveTile{i, bx, by, bz});
             std::memset(&gargs[i], 0, sizeof(gargs[i]));
             std::memset(&halo[i], 0, sizeof(halo[i]));  // nx = 0: the fill skips it
             rows[i] = 0;
@@ -184,6 +185,46 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         gargs[i].nxt = nxt[i];
         rows[i] = (T_steps + H - 1) / H + 1;  // rows 0 .. rho_max
         max_rows = std::max(max_rows, rows[i]);
+    }
+    // naive grids in groups whose arrays fit the last-level cache; a group
+    // runs all T steps before the next one starts
+    std::vector<std::pair<int, int>> ngroups;  // (first table entry, count)
+    {
+        std::vector<int> nidx;
+        for (int i = 0; i < n; ++i)
+            if (var[i] < 0) nidx.push_back(i);
+        size_t k = 0;
+        while (k < nidx.size()) {
+            size_t bytes = 0, k1 = k;
+            while (k1 < nidx.size()) {
+                const stencil_grid& gg = grids[nidx[k1]];
+                const size_t gb = (size_t)(2 + narr_of(hw[nidx[k1]].kind)) * (size_t)gg.sz *
+                                  (size_t)(gg.nz + 2 * gg.halo) * es_of(dtype);
+                if (k1 > k && bytes + gb > kCacheGroupBytes) break;
+                bytes += gb;
+                ++k1;
+            }
+            // z chunks short enough that a group's launch has work for
+            // every CU several times over
+            long long cols = 0;
+            for (size_t q = k; q < k1; ++q) {
+                const stencil_grid& gg = grids[nidx[q]];
+                cols += (long long)((gg.nx + kNaiveBX - 1) / kNaiveBX) * ((gg.ny + kNaiveBY - 1) / kNaiveBY) * gg.nz;
+            }
+            int zc = 64;
+            while (zc > 16 && cols / zc < kNaiveMinBlocks) zc /= 2;
+            const int first = (int)ntiles.size();
+            for (size_t q = k; q < k1; ++q) {
+                const int i = nidx[q];
+                NaiveArgs<T>& na = nargs[i];
+                na.zchunk = zc;
+                for (int bz = 0; bz * zc < na.nz; ++bz)
+                    for (int by = 0; by * kNaiveBY < na.ny; ++by)
+                        for (int bx = 0; bx * kNaiveBX < na.nx; ++bx) ntiles.push_back(NaiveTile{i, bx, by, bz});
+            }
+            ngroups.emplace_back(first, (int)ntiles.size() - first);
+            k = k1;
+        }
     }
     std::vector<int> group_first;  // table index where each row group starts
     for (int rho = 0; rho < max_rows; ++rho) {
@@ -267,11 +308,13 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         const dim3 hgrid(hgx, hgy, n);
         hipError_t el = sizeof(T) == 8 ? batch_halo_launch_f64(reinterpret_cast<const HaloFill<double>*>(d_halo), hgrid, cs)
                                        : batch_halo_launch_f32(reinterpret_cast<const HaloFill<float>*>(d_halo), hgrid, cs);
-        // the naive grids: one launch per time step, all grids together
-        for (int t = 0; t < T_steps && !ntiles.empty() && el == hipSuccess; ++t) {
-            NaiveLaunch<T> NL{d_ntiles, d_nargs, t};
-            if constexpr (sizeof(T) == 8) el = batch_naive_launch_f64(NL, (int)ntiles.size(), cs);
-            else el = batch_naive_launch_f32(NL, (int)ntiles.size(), cs);
+        // the naive grids: group by group, one launch per time step
+        for (const auto& ng : ngroups) {
+            for (int t = 0; t < T_steps && ng.second > 0 && el == hipSuccess; ++t) {
+                NaiveLaunch<T> NL{d_ntiles, d_nargs, ng.first, t};
+                if constexpr (sizeof(T) == 8) el = batch_naive_launch_f64(NL, ng.second, cs);
+                else el = batch_naive_launch_f32(NL, ng.second, cs);
+            }
         }
         for (size_t g = 0; g + 1 < group_first.size() && el == hipSuccess; ++g) {
             const int cnt = group_first[g + 1] - group_first[g];

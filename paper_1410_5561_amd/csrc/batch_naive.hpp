@@ -1,8 +1,11 @@
-// Batched naive sweep: one launch per time step advances every naive-planned
-// grid of a batch by one step; a workgroup takes one (grid, x block, y block,
-// z chunk) entry of a table.  Used, inside the batch's hipGraph, for the grids
-// the tuner finds faster without temporal blocking (small grids, where MWD
-// tiles are mostly overlap and edge).
+// Batched naive sweep: one launch advances a group of naive-planned grids of
+// a batch by one step; a workgroup takes one (grid, x block, y block, z
+// chunk) entry of a table.  Used, inside the batch's hipGraph, for the grids
+// the tuner finds faster without MWD tiles (small grids, where the tiles are
+// mostly overlap and edge).  The grids are grouped so that a group's arrays
+// fit the GPU's last-level (Infinity) cache, and each group takes all T steps
+// before the next starts: temporal blocking in that cache, the same aim as
+// the diamonds' blocking in registers and LDS (Sec. II).
 #pragma once
 
 #include "naive_block.hpp"
@@ -27,13 +30,14 @@ template <typename T>
 struct NaiveLaunch {
     const NaiveTile* tiles;
     const NaiveArgs<T>* args;
-    int t;  // step of this launch: reads level t, writes level t + 1
+    int first;  // first table entry of this launch
+    int t;      // step of this launch: reads level t, writes level t + 1
 };
 
 template <typename T>
 __device__ __forceinline__ void batch_naive_tile(const NaiveLaunch<T>& L, char* lds)
 {
-    const NaiveTile e = L.tiles[blockIdx.x];
+    const NaiveTile e = L.tiles[L.first + blockIdx.x];
     const NaiveArgs<T>& a = L.args[e.grid];
     const T* src = a.buf[(a.cur + L.t) & 1];
     T* dst = a.buf[(a.cur + L.t + 1) & 1];

@@ -3,7 +3,9 @@
 
 namespace mwd {
 
-__global__ void __launch_bounds__(kNaiveBX * kNaiveBY)
+// Two 1024-thread workgroups per CU (8 waves per SIMD: at most 64 registers),
+// so that one workgroup's barriers overlap the other's work.
+__global__ void __launch_bounds__(kNaiveBX * kNaiveBY, 8)
 batch_naive_kernel_f32(NaiveLaunch<float> L)
 {
     __shared__ __attribute__((aligned(16))) char lds[naive_lds_bytes<float>()];
