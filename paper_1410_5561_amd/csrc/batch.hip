@@ -53,8 +53,10 @@ static size_t es_of(int dtype) { return dtype == 0 ? 8 : 4; }
 
 // run of adjacent tiles given to one XCD in a batched row group
 constexpr int kBatchXcdRun = 4;
-// arrays of one group of naive grids: within the 256 MiB last-level cache
-constexpr size_t kCacheGroupBytes = size_t(160) << 20;
+// arrays of one group of naive grids; kNaiveBranches groups run at a time,
+// together within the 256 MiB last-level cache
+constexpr size_t kCacheGroupBytes = size_t(96) << 20;
+constexpr int kNaiveBranches = 2;
 // workgroups per launch below which a group's z chunks are halved
 constexpr long long kNaiveMinBlocks = 2048;
 
@@ -302,19 +304,53 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         *errmsg = std::string("stream: ") + hipGetErrorString(e);
         return STENCIL_EDEVICE;
     }
+    // branch streams and fork/join events for the naive groups
+    hipStream_t bstreams[kNaiveBranches - 1] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kNaiveBranches - 1] = {};
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming);
+    for (int b = 0; b < kNaiveBranches - 1 && e == hipSuccess; ++b) {
+        e = hipStreamCreateWithFlags(&bstreams[b], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&join_ev[b], hipEventDisableTiming);
+    }
+    auto release_branches = [&]() {
+        for (int b = 0; b < kNaiveBranches - 1; ++b) {
+            if (bstreams[b]) (void)hipStreamDestroy(bstreams[b]);
+            if (join_ev[b]) (void)hipEventDestroy(join_ev[b]);
+        }
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+    };
+    if (e != hipSuccess) {
+        release_branches();
+        (void)hipStreamDestroy(cs);
+        *errmsg = std::string("stream: ") + hipGetErrorString(e);
+        return STENCIL_EDEVICE;
+    }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         // boundary band into the scratch pairs first (each entry checks its own extent)
         const dim3 hgrid(hgx, hgy, n);
         hipError_t el = sizeof(T) == 8 ? batch_halo_launch_f64(reinterpret_cast<const HaloFill<double>*>(d_halo), hgrid, cs)
                                        : batch_halo_launch_f32(reinterpret_cast<const HaloFill<float>*>(d_halo), hgrid, cs);
-        // the naive grids: group by group, one launch per time step
-        for (const auto& ng : ngroups) {
+        // the naive grids: group by group, one launch per time step; the
+        // groups alternate between kNaiveBranches concurrent graph branches
+        // (forked from and joined back into the capturing stream), so that
+        // one group's launch gaps and tails overlap another group's work
+        if (el == hipSuccess && !ngroups.empty()) el = hipEventRecord(fork_ev, cs);
+        for (int b = 0; b < kNaiveBranches - 1 && el == hipSuccess && !ngroups.empty(); ++b)
+            el = hipStreamWaitEvent(bstreams[b], fork_ev, 0);
+        for (size_t gi = 0; gi < ngroups.size() && el == hipSuccess; ++gi) {
+            const auto& ng = ngroups[gi];
+            const int br = (int)(gi % kNaiveBranches);
+            hipStream_t st = br == 0 ? cs : bstreams[br - 1];
             for (int t = 0; t < T_steps && ng.second > 0 && el == hipSuccess; ++t) {
                 NaiveLaunch<T> NL{d_ntiles, d_nargs, ng.first, t};
-                if constexpr (sizeof(T) == 8) el = batch_naive_launch_f64(NL, ng.second, cs);
-                else el = batch_naive_launch_f32(NL, ng.second, cs);
+                if constexpr (sizeof(T) == 8) el = batch_naive_launch_f64(NL, ng.second, st);
+                else el = batch_naive_launch_f32(NL, ng.second, st);
             }
+        }
+        for (int b = 0; b < kNaiveBranches - 1 && el == hipSuccess && !ngroups.empty(); ++b) {
+            el = hipEventRecord(join_ev[b], bstreams[b]);
+            if (el == hipSuccess) el = hipStreamWaitEvent(cs, join_ev[b], 0);
         }
         for (size_t g = 0; g + 1 < group_first.size() && el == hipSuccess; ++g) {
             const int cnt = group_first[g + 1] - group_first[g];
@@ -327,6 +363,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         if (e == hipSuccess && el != hipSuccess) e = el;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0);
+    release_branches();
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
         *errmsg = std::string("graph capture: ") + hipGetErrorString(e);
