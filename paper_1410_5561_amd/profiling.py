@@ -36,7 +36,7 @@ _KERNEL_SOURCES = {
                        "mwd_inst_7c_f64.hip", "mwd_inst_7c_f32.hip", "mwd_inst_7v_f64.hip",
                        "mwd_inst_7v_f32.hip", "mwd_inst_25c_f64.hip", "mwd_inst_25c_f32.hip",
                        "mwd_inst_25v_f64.hip", "mwd_inst_25v_f32.hip"],
-    "naive_sweep_kernel": ["naive.hip", "common.hpp", "internal.hpp"],
+    "naive_sweep_kernel": ["naive.hip", "naive_block.hpp", "common.hpp", "internal.hpp"],
 }
 
 
