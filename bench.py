@@ -86,19 +86,21 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
     plan.profile(True)
     plan.profile_read()  # drop anything recorded so far
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
+    evs[0].record(stream)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         plan.run(g, c, T)
-    e1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev = e0.elapsed_time(e1) / 1e3
+    ev = evs[0].elapsed_time(evs[-1]) / 1e3
+    per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     prof = plan.profile_read()
     desc = plan.describe()
+    desc["step_ms"] = {"min": round(per_step[0], 4), "median": round(per_step[len(per_step) // 2], 4),
+                       "max": round(per_step[-1], 4)}
     state = (a, b)[g.cur]
     plan.close()
     return max(ev, 1e-9), wall, desc, prof, state
@@ -119,7 +121,17 @@ def cpu_baseline(w, dtype, windex, T_cpu):
     oracle.run(w["kind"], u0, co, T_cpu, halo=R, threads=threads)
     dt = time.perf_counter() - t0
     lups = nx * ny * nz * T_cpu
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": lups / dt / 1e9, "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu, "host_cpus": os.cpu_count(),
             "sample": "%s, full %dx%dx%d grid, T=%d (of %d), %.1f s" % (
                 w["kind"] + "-" + dtype, nx, ny, nz, T_cpu, w["T"], dt)}
 
@@ -235,6 +247,7 @@ def main():
                    "lups_per_step": lups},
         "schedule": {"mode": mode_name, "dw": desc["dw"], "lanes": desc["lanes"],
                      "xtile": desc["xtile"], "levels": desc["levels"]},
+        "step_ms": desc["step_ms"],
         "model_bytes_per_lup": round(model_bpl, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
