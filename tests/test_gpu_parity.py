@@ -79,6 +79,22 @@ def test_mwd_bitexact(case):
     _check(kind, u0, co, T, *got)
 
 
+@pytest.mark.parametrize("case", MWD_CASES, ids=lambda c: "%s-%s-dw%d-lx%d" % c)
+def test_mwd_bitexact_steady_state(case):
+    """Deep enough in z that the tile runs several chunks of its steady-state
+    step body (every plane inside the domain) between the checked boundary
+    steps, wide enough in x and y that some tiles have no lane outside the
+    domain and others straddle each edge."""
+    kind, dts, dw, lanes = case
+    dtype = np.float64 if dts == "f64" else np.float32
+    n = (160, 40, 70) if kind in ("7c", "7v") else (150, 60, 70)
+    T = 6
+    print("mwd steady", case, n, T, flush=True)
+    u0, co = _inputs(kind, n, dtype, seed=23)
+    got = run_gpu(kind, u0, co, T, mode="mwd", dw=dw, lanes=lanes)
+    _check(kind, u0, co, T, *got)
+
+
 @pytest.mark.parametrize("T", [0, 1, 2, 3, 4, 5, 8, 9])
 @pytest.mark.parametrize("cur", [0, 1])
 def test_mwd_step_counts_and_cur(T, cur):
