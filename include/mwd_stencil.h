@@ -55,7 +55,7 @@ typedef enum {
 typedef enum { STENCIL_F64 = 0, STENCIL_F32 = 1 } stencil_dtype;
 
 typedef enum {
-    STENCIL_MODE_AUTO = 0,  /* let the plan choose (autotuned once per size bucket)           */
+    STENCIL_MODE_AUTO = 0,  /* let the plan choose (autotuned once per size and T)            */
     STENCIL_MODE_NAIVE = 1, /* one full sweep per time step                                   */
     STENCIL_MODE_MWD = 2    /* wavefront diamond temporal blocking                            */
 } stencil_mode;
@@ -110,8 +110,9 @@ typedef struct {
 /* Create a plan for grids of the given kind, dtype and interior size
  * (STENCIL_KIND_MIXED with nx = ny = nz = 0 for batched plans).  p == NULL
  * asks for the autotuned schedule (Sec. II-A: parameters are auto-tuned);
- * tuning runs on scratch grids the plan allocates, at the first
- * stencil_run.  Errors: EINVAL (bad kind/dtype/size/params), EUNSUPPORTED
+ * tuning runs at the first stencil_run (synchronously, on a proxy grid of
+ * the same x-y extent that it allocates and frees), predicting the whole run
+ * for that call's T; the choice is kept for the plan's later runs.  Errors: EINVAL (bad kind/dtype/size/params), EUNSUPPORTED
  * (parameters no kernel implements), ENOMEM. */
 int stencil_create(stencil_plan **out, int32_t kind, int32_t dtype,
                    int32_t nx, int32_t ny, int32_t nz, const stencil_params *p);
@@ -130,21 +131,26 @@ int stencil_run(stencil_plan *plan, stencil_grid *grid, const stencil_coeffs *co
 /* Release a plan: waits for its work, frees its scratch and graphs. */
 int stencil_destroy(stencil_plan *plan);
 
-/* Advance n independent grids (uneven sizes, kinds 7c/25c in both dtypes,
- * 7v in FP32; one dtype per call) by T steps with ONE hipGraph launch.  The
- * MWD tiles of all grids are grouped by diamond row; each group is one kernel
- * launch (a workgroup per tile, any grid), and the group launches plus a
- * final gather are captured into a graph once and replayed (kernel
- * boundaries are the row-to-row dependencies; no workgroup waits on
- * another).  Diamond width and x lanes are autotuned per (kind, size bucket)
- * among the shapes compiled into the batched kernel.  The first call for a
- * given set of grids builds the tile table, allocates scratch (two extra
- * buffer pairs per grid) and captures the graph; later calls with the same
- * grids (same pointers, sizes, weights and cur) replay it; two such sets are
- * cached.  Asynchronous on `stream`; on return every grids[i].cur is updated
- * as by stencil_run.  The plan must have been created with
- * STENCIL_KIND_MIXED or the grids' common kind.  Errors: as stencil_run;
- * EUNSUPPORTED for a kind/dtype without a batched tile shape. */
+/* Advance n independent grids (1 <= n <= 65535; uneven sizes, any kind; one
+ * dtype per call) by T steps with ONE hipGraph launch (batched form of the
+ * MWD method, Sec. II-A).  Per grid the plan picks, by kind and size bucket
+ * (autotuned once), either:
+ *  - MWD tiles: the tiles of all such grids are grouped by diamond row, one
+ *    kernel launch per group (a workgroup per tile, any grid), then a gather;
+ *    kernel boundaries are the row-to-row dependencies.  Shapes: 7c and 25c
+ *    in both dtypes, 7v in FP32 (those compiled into the batched kernel);
+ *  - the naive sweep: grids grouped so that a group's arrays fit the GPU's
+ *    last-level cache, each group taking its T one-step launches before the
+ *    next group starts; groups alternate between two concurrent branches.
+ * No workgroup waits on another.  The first call for a given set of grids
+ * builds the tables, allocates scratch (two extra buffer pairs per MWD grid)
+ * and captures the graph; later calls with the same grids (same pointers,
+ * sizes, weights and cur) replay it; two such sets are cached.  Asynchronous
+ * on `stream`; on return every grids[i].cur is updated as by stencil_run.
+ * The plan must have been created with STENCIL_KIND_MIXED or the grids'
+ * common kind.  MWD_TUNE=naive or MWD_TUNE=mwd (environment) forces every
+ * grid onto one of the two schedules (a kind without a batched tile shape
+ * stays naive).  Errors: as stencil_run; EINVAL for n outside 1..65535. */
 int stencil_run_batched(stencil_plan *plan, stencil_grid *grids, const stencil_coeffs *coeffs,
                         int32_t n, int32_t T, void *stream);
 

@@ -1,4 +1,4 @@
-// Batched form: many grids in one persistent, graph-captured launch.
+// Batched form: many grids advanced together by one captured hipGraph.
 #pragma once
 
 #include <hip/hip_runtime.h>
