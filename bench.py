@@ -101,9 +101,63 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
     desc = plan.describe()
     desc["step_ms"] = {"min": round(per_step[0], 4), "median": round(per_step[len(per_step) // 2], 4),
                        "max": round(per_step[-1], 4)}
+    # FP64 norms (on the GPU) of the last level and of the last step's change
+    l2, mx = S.stencil_norms(g, 0)
+    rl2, rmx = S.stencil_norms(g, 1)
+    desc["norms"] = {"u_l2": l2, "u_max": mx, "residual_l2": rl2, "residual_max": rmx}
     state = (a, b)[g.cur]
     plan.close()
     return max(ev, 1e-9), wall, desc, prof, state
+
+
+FLOPS_PER_LUP = {"7c": 10, "7v": 13, "25c": 37, "25v": 37}
+
+
+def precision_subrun(S, torch, w, windex, n=(256, 256, 256)):
+    """The FP32 form against FP64 on a sub-run of the workload (same kind, T
+    and seed, an n-point interior): both runs on the GPU from the same FP64
+    draws (the FP32 inputs are their casts), the difference's norms reduced
+    in FP64 on the GPU.  The FP64 run is the oracle's result (bit-exact, as
+    the parity tests check).
+
+    A priori bound: every weight set here is non-negative with sum <= 1, so
+    one sweep does not amplify an error in the max norm and keeps |u| below
+    |u0|max; each sweep adds at most ops rounding errors of unit 2^-24 on its
+    terms plus one from the FP32 weights, and the cast of u0 adds one more:
+    (T * (ops + 1) + 1) * 2^-24 * |u0|max, ops = the flops of one update."""
+    import gridgen
+    kind, T = w["kind"], w["T"]
+    R = gridgen.RADIUS[kind]
+    seed = gridgen.seed_for_config(windex)
+    u64 = gridgen.field(seed, *n, R, *w["field"], dtype=np.float64)
+    if w["coeffs"] == "7v":
+        c64 = gridgen.coeffs_7v(seed, *n, R, dtype=np.float64)
+    else:
+        c64 = list(w["coeffs"])
+    out = {}
+    for dt, npdt in (("f64", np.float64), ("f32", np.float32)):
+        a = torch.from_numpy(u64.astype(npdt)).cuda()
+        b = a.clone()
+        g = S.make_grid(a, b, R, 0)
+        if kind in ("7c", "25c"):
+            cdev = None
+            c = S.make_coeffs(kind, consts=[float(npdt(x)) for x in c64])
+        else:
+            cdev = [torch.from_numpy(x.astype(npdt)).cuda() for x in c64]
+            c = S.make_coeffs(kind, arrays=cdev)
+        plan = S.Plan(kind, dt, *n)
+        plan.run(g, c, T)
+        torch.cuda.synchronize()
+        plan.close()
+        out[dt] = (g, (a, b), cdev)
+    err_l2, err_max = S.stencil_diff_norms(out["f32"][0], out["f64"][0])
+    ref_l2, ref_max = S.stencil_norms(out["f64"][0], 0)
+    u0max = float(np.max(np.abs(u64)))
+    bound = (T * (FLOPS_PER_LUP[kind] + 1) + 1) * 2.0 ** -24 * u0max
+    return {"sub_run": "%s %dx%dx%d T=%d, seed of the workload" % (kind, n[0], n[1], n[2], T),
+            "max_abs_err": err_max, "max_rel_err": err_max / ref_max if ref_max else err_max,
+            "l2_rel_err": err_l2 / ref_l2 if ref_l2 else err_l2,
+            "a_priori_bound": bound, "within_bound": bool(err_max <= bound)}
 
 
 def cpu_baseline(w, dtype, windex, T_cpu, min_s=10.0, max_reps=20):
@@ -255,6 +309,7 @@ def main():
         "schedule": {"mode": mode_name, "dw": desc["dw"], "lanes": desc["lanes"],
                      "xtile": desc["xtile"], "levels": desc["levels"]},
         "step_ms": desc["step_ms"],
+        "norms_fp64": desc["norms"],
         "model_bytes_per_lup": round(model_bpl, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -292,6 +347,10 @@ def main():
                        "GBs_at_model": round(sv * sdesc["model_bytes_per_lup"], 1)})
             log(a, "sweep", sw[-1])
         out["sweep"] = sw
+    if dtype == "f32":
+        log(a, "precision sub-run")
+        out["fp32_vs_fp64"] = precision_subrun(S, torch, w, a.workload,
+                                                n=tuple(w.get("error_subrun", (256, 256, 256))))
     # practical bandwidth reference: streaming copy of 2 GiB
     nbytes = 1 << 31
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
