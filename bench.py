@@ -115,16 +115,19 @@ FLOPS_PER_LUP = {"7c": 10, "7v": 13, "25c": 37, "25v": 37}
 
 def precision_subrun(S, torch, w, windex, n=(256, 256, 256)):
     """The FP32 form against FP64 on a sub-run of the workload (same kind, T
-    and seed, an n-point interior): both runs on the GPU from the same FP64
-    draws (the FP32 inputs are their casts), the difference's norms reduced
-    in FP64 on the GPU.  The FP64 run is the oracle's result (bit-exact, as
-    the parity tests check).
+    and seed, an n-point interior), all on the GPU, the difference's norms
+    reduced in FP64 on the GPU.  Three runs: FP32 on the casts of the FP64
+    draws; FP64 on those same FP32-rounded inputs, widened (the primary
+    reference: it isolates the FP32 arithmetic); FP64 on the original draws
+    (the error of choosing FP32 at all).  The FP64 runs are the oracle's
+    results (bit-exact, as the parity tests check).
 
-    A priori bound: every weight set here is non-negative with sum <= 1, so
+    A priori bounds: every weight set here is non-negative with sum <= 1, so
     one sweep does not amplify an error in the max norm and keeps |u| below
-    |u0|max; each sweep adds at most ops rounding errors of unit 2^-24 on its
-    terms plus one from the FP32 weights, and the cast of u0 adds one more:
-    (T * (ops + 1) + 1) * 2^-24 * |u0|max, ops = the flops of one update."""
+    |u0|max; each sweep adds at most ops roundings of unit 2^-24 (ops = the
+    flops of one update), plus one on the FP64 side's behalf: T * (ops + 1)
+    * 2^-24 * |u0|max.  Against the original draws the FP32 weights add one
+    more per sweep and the cast of u0 one in all."""
     import gridgen
     kind, T = w["kind"], w["T"]
     R = gridgen.RADIUS[kind]
@@ -134,30 +137,42 @@ def precision_subrun(S, torch, w, windex, n=(256, 256, 256)):
         c64 = gridgen.coeffs_7v(seed, *n, R, dtype=np.float64)
     else:
         c64 = list(w["coeffs"])
+
+    def widened(x):
+        return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+    runs = {"f32": ("f32", u64.astype(np.float32),
+                    [np.asarray(c, dtype=np.float32) for c in c64]),
+            "f64_on_f32_inputs": ("f64", widened(u64), [widened(c) for c in c64]),
+            "f64": ("f64", u64, [np.asarray(c, dtype=np.float64) for c in c64])}
     out = {}
-    for dt, npdt in (("f64", np.float64), ("f32", np.float32)):
-        a = torch.from_numpy(u64.astype(npdt)).cuda()
+    for name, (dt, u0, co) in runs.items():
+        a = torch.from_numpy(u0).cuda()
         b = a.clone()
         g = S.make_grid(a, b, R, 0)
         if kind in ("7c", "25c"):
             cdev = None
-            c = S.make_coeffs(kind, consts=[float(npdt(x)) for x in c64])
+            c = S.make_coeffs(kind, consts=[float(x) for x in co])
         else:
-            cdev = [torch.from_numpy(x.astype(npdt)).cuda() for x in c64]
+            cdev = [torch.from_numpy(x).cuda() for x in co]
             c = S.make_coeffs(kind, arrays=cdev)
         plan = S.Plan(kind, dt, *n)
         plan.run(g, c, T)
         torch.cuda.synchronize()
         plan.close()
-        out[dt] = (g, (a, b), cdev)
-    err_l2, err_max = S.stencil_diff_norms(out["f32"][0], out["f64"][0])
-    ref_l2, ref_max = S.stencil_norms(out["f64"][0], 0)
+        out[name] = (g, (a, b), cdev)
     u0max = float(np.max(np.abs(u64)))
-    bound = (T * (FLOPS_PER_LUP[kind] + 1) + 1) * 2.0 ** -24 * u0max
-    return {"sub_run": "%s %dx%dx%d T=%d, seed of the workload" % (kind, n[0], n[1], n[2], T),
-            "max_abs_err": err_max, "max_rel_err": err_max / ref_max if ref_max else err_max,
-            "l2_rel_err": err_l2 / ref_l2 if ref_l2 else err_l2,
-            "a_priori_bound": bound, "within_bound": bool(err_max <= bound)}
+    ops = FLOPS_PER_LUP[kind]
+    res = {"sub_run": "%s %dx%dx%d T=%d, seed of the workload" % (kind, n[0], n[1], n[2], T)}
+    for ref, bound in (("f64_on_f32_inputs", T * (ops + 1) * 2.0 ** -24 * u0max),
+                       ("f64", (T * (ops + 2) + 1) * 2.0 ** -24 * u0max)):
+        err_l2, err_max = S.stencil_diff_norms(out["f32"][0], out[ref][0])
+        ref_l2, ref_max = S.stencil_norms(out[ref][0], 0)
+        res["vs_" + ref] = {"max_abs_err": err_max,
+                            "max_rel_err": err_max / ref_max if ref_max else err_max,
+                            "l2_rel_err": err_l2 / ref_l2 if ref_l2 else err_l2,
+                            "a_priori_bound": bound, "within_bound": bool(err_max <= bound)}
+    return res
 
 
 def cpu_baseline(w, dtype, windex, T_cpu, min_s=10.0, max_reps=20):

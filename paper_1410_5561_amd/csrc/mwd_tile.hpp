@@ -87,6 +87,87 @@ __device__ __forceinline__ int opaque_uniform(int v)
 // becoming per-lane selects.
 __device__ __forceinline__ void keep_branch() { asm volatile(""); }
 
+// Level sets of the diamond rows of a tile that no clipping touches (every
+// row inside the domain, every level inside 1 .. T).  Row yr of such a tile
+// computes level tau iff its distance d from the diamond's centre satisfies
+// d < R min(tau, 2h - tau); it holds (publishes) level tau if it computes it
+// or a row within R of it computes tau + 1; it stores its top two computed
+// levels.  Rows with equal sets share one row type; the steady-state body is
+// compiled once per type with these sets as constants, so that a wave of such
+// a tile runs no per-level tests.
+template <int R, int DW, int H, int L>
+struct CanonRows {
+    static constexpr bool computed(int yrr, int tau)
+    {
+        if (tau < 1 || tau > L || yrr < 0 || yrr >= DW) return false;
+        const int d = yrr < DW / 2 ? DW / 2 - 1 - yrr : yrr - DW / 2;
+        return d < R * (tau < 2 * H - tau ? tau : 2 * H - tau);
+    }
+    static constexpr uint32_t cmask(int yr)
+    {
+        uint32_t m = 0;
+        for (int tau = 0; tau <= L; ++tau)
+            if (computed(yr, tau)) m |= 1u << tau;
+        return m;
+    }
+    static constexpr uint32_t pmask(int yr)
+    {
+        uint32_t m = cmask(yr);
+        for (int tau = 0; tau < L; ++tau)
+            for (int dy = -R; dy <= R; ++dy)
+                if (computed(yr + dy, tau + 1)) m |= 1u << tau;
+        return m;
+    }
+    static constexpr uint32_t smask(int yr)
+    {
+        const uint32_t c = cmask(yr);
+        int thi = -1;
+        for (int tau = 0; tau <= L; ++tau)
+            if ((c >> tau) & 1u) thi = tau;
+        uint32_t m = 0;
+        for (int tau = 0; tau <= L; ++tau)
+            if (((c >> tau) & 1u) && tau >= thi - 1) m |= 1u << tau;
+        return m;
+    }
+    static constexpr bool same(int a, int b)
+    {
+        return cmask(a) == cmask(b) && pmask(a) == pmask(b) && smask(a) == smask(b);
+    }
+    static constexpr bool first_of_type(int yr)
+    {
+        for (int o = 0; o < yr; ++o)
+            if (same(o, yr)) return false;
+        return true;
+    }
+    static constexpr int ntypes()
+    {
+        int n = 0;
+        for (int yr = 0; yr < DW; ++yr)
+            if (first_of_type(yr)) ++n;
+        return n;
+    }
+    // a row of type i
+    static constexpr int rep(int i)
+    {
+        for (int yr = 0, n = 0; yr < DW; ++yr)
+            if (first_of_type(yr) && n++ == i) return yr;
+        return -1;
+    }
+    static constexpr int lowbit(uint32_t m)
+    {
+        for (int b = 0; b < 32; ++b)
+            if ((m >> b) & 1u) return b;
+        return -1;
+    }
+    // edge levels (held, not computed) of type i, -1: none
+    static constexpr int ta(int i) { return lowbit(pmask(rep(i)) & ~cmask(rep(i))); }
+    static constexpr int tb(int i)
+    {
+        const uint32_t e = pmask(rep(i)) & ~cmask(rep(i));
+        return lowbit(e & (e - 1u));
+    }
+};
+
 // Which buffer pair holds the levels written by row rho.
 __host__ __device__ __forceinline__ int pair_of_row(int rho) { return (rho + 1) % 3; }
 
@@ -318,19 +399,44 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
     const int par0 = (a.cur + row.t0) & 1;  // buffer of the even levels
     const int ea = has_a ? ta : -1, eb_ = has_b ? tb : -1;  // edge levels, -1: none
 
-    // One wavefront step.  FAST: a steady-state step (see above).
-    auto step = [&](auto uc, auto fc, int s, const char* const* cb) MWD_INLINE {
+    // One wavefront step.  FAST: a steady-state step (see above).  ti: the
+    // wave's row type (its level sets as constants), or -1 (any row).
+    using CR = CanonRows<R, DW, H, L>;
+    auto step = [&](auto uc, auto fc, auto ti, int s, const char* const* cb) MWD_INLINE {
         constexpr int u = decltype(uc)::value;
         constexpr bool FAST = decltype(fc)::value;
+        constexpr int TI = decltype(ti)::value;
+        constexpr bool CAN = TI >= 0;
+        static_assert(!CAN || FAST, "row types are for steady-state steps");
         constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
         const int eb = s & 1;
-        // the wave's level sets, re-read at every step so that the per-level
-        // tests below stay scalar compares instead of lane masks held (and
-        // spilled) across the loop
-        const uint32_t cm = (uint32_t)opaque_uniform((int)cmask);
-        const uint32_t pm = (uint32_t)opaque_uniform((int)pmask);
-        const uint32_t sm = (uint32_t)opaque_uniform((int)smask);
-        const int e1 = opaque_uniform(ea), e2 = opaque_uniform(eb_);
+        if constexpr (CAN) asm volatile("; row type %0" ::"n"(TI));
+        // the wave's level sets: constants for a row type; otherwise re-read
+        // at every step so that the per-level tests below stay scalar
+        // compares instead of lane masks held (and spilled) across the loop
+        uint32_t cm, pm, sm;
+        int e1, e2;
+        bool hasa, hasb;
+        if constexpr (CAN) {
+            constexpr int yt = CR::rep(CAN ? TI : 0);
+            constexpr uint32_t CM = CR::cmask(yt), PM = CR::pmask(yt), SM = CR::smask(yt);
+            constexpr int TA = CR::ta(CAN ? TI : 0), TB = CR::tb(CAN ? TI : 0);
+            cm = CM;
+            pm = PM;
+            sm = SM;
+            e1 = TA;
+            e2 = TB;
+            hasa = TA >= 0;
+            hasb = TB >= 0;
+        } else {
+            cm = (uint32_t)opaque_uniform((int)cmask);
+            pm = (uint32_t)opaque_uniform((int)pmask);
+            sm = (uint32_t)opaque_uniform((int)smask);
+            e1 = opaque_uniform(ea);
+            e2 = opaque_uniform(eb_);
+            hasa = has_a;
+            hasb = has_b;
+        }
         qtop_prev = qtop;  // level L's plane s - 1 - LR, for this step's stores
         // plane s - 1 - tau R of level tau (the previous step's), for the stores
         auto qold = [&](auto tc) MWD_INLINE -> T {
@@ -345,8 +451,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         static_for<0, L>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             const int p = s - (tau + 1) * R;
-            if (FAST || (((pm >> tau) & 1u) && p >= 0 && p < a.nz))
-                ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
+            const bool pub = CAN ? ((pm >> tau) & 1u) != 0u
+                                 : (FAST || (((pm >> tau) & 1u) && p >= 0 && p < a.nz));
+            if (pub) ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
         });
         // side row: unconditional, so the wait for its load is the same on
         // every path
@@ -367,9 +474,14 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             }
         });
         // boundary values: lanes outside the domain, and, outside the steady
-        // state, every lane of a level whose plane is a boundary plane
+        // state, every lane of a level whose plane is a boundary plane.  Each
+        // level copies the level below at the same plane, which is final
+        // before this step, so the copy may come before or after the
+        // computation: a row type computes every lane (lanes outside the
+        // domain compute values nobody reads) and copies afterwards.
         const bool bnd_planes = !FAST && (s - L * R < 0 || s >= a.nz);
-        if (wave_bnd || bnd_planes) {
+        auto boundary = [&]() MWD_INLINE {
+          if (wave_bnd || bnd_planes) {
             static_for<0, L + 1>([&](auto tc) MWD_INLINE {
                 constexpr int tau = decltype(tc)::value;
                 const int p = s - tau * R;
@@ -383,7 +495,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                     if (bnd) q[tau][cmod(u - tau * R, Q)] = bv;
                 }
             });
-        }
+          }
+        };
+        if constexpr (!CAN) boundary();
         // (3) stores of the previous step (its values are still in the
         //     queues): the last two levels of each point.  Issued before this
         //     step's loads, so waits on those loads stay exact.
@@ -415,8 +529,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             const uint32_t du = opaque_u32((uint32_t)(u * szb));
             const uint32_t o = colb + du;
             if (sv_present) sv[k] = ld(cb[0], off_s + du);
-            if (has_a) lea[k] = ld(cb[1], o);
-            if (has_b) leb[k] = ld(cb[2], o);
+            if (hasa) lea[k] = ld(cb[1], o);
+            if (hasb) leb[k] = ld(cb[2], o);
             if (wave_bnd) bzr[k] = ld(cb[3], o);
             if constexpr (NARR > 0) {
                 constexpr int PD = G::PD;
@@ -459,7 +573,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         constexpr bool XYPF = R == 1 && (L <= 3 || (sizeof(T) == 4 && L <= 7));
         T xy[XYPF ? L + 1 : 1][4];
         if constexpr (XYPF) {
-            if (xl >= R && xl < LX - R) {
+            if (CAN || (xl >= R && xl < LX - R)) {
                 static_for<1, L + 1>([&](auto tc) MWD_INLINE {
                     constexpr int tau = decltype(tc)::value;
                     xy[tau][0] = ex[eb][tau - 1][yr + R][xl + 1];
@@ -473,7 +587,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             constexpr int tau = decltype(tc)::value;
             const int p = s - tau * R;
             if (((cm >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
-                if (xin && xl >= tau * R && xl < LX - tau * R) {
+                // a row type computes every lane: a lane outside the level's
+                // x range reads in-bounds LDS and its value is never read
+                if (CAN || (xin && xl >= tau * R && xl < LX - tau * R)) {
                     auto nb = [&](int dx, int dy, int dz) MWD_INLINE -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
                         if constexpr (XYPF) {
@@ -498,17 +614,19 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 }
             }
         });
+        if constexpr (CAN) boundary();
     };
 
     const char* const nocb[1] = {nullptr};
     auto generic_chunks = [&](int from, int to) MWD_INLINE {
         for (int sb = from; sb < to; sb += U)
             static_for<0, U>([&](auto uc) MWD_INLINE {
-                step(uc, std::false_type{}, opaque_uniform(sb + decltype(uc)::value), nocb);
+                step(uc, std::false_type{}, std::integral_constant<int, -1>{}, opaque_uniform(sb + decltype(uc)::value), nocb);
             });
     };
     generic_chunks(s_first, s_fast_begin);
-    for (int sb = s_fast_begin; sb < s_fast_end; sb += U) {
+    auto fast_chunks = [&](auto ti) MWD_INLINE {
+      for (int sb = s_fast_begin; sb < s_fast_end; sb += U) {
         const int pl = sb + PL;
         const char* cb[6 + (NARR > 0 ? NARR : 1)];
         cb[0] = plane(sv_src, pl - H * R);
@@ -521,8 +639,21 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
 #pragma unroll
             for (int m = 0; m < NARR; ++m) cb[6 + m] = plane(a.w.arr[m], sb + G::PD - R);
         }
-        static_for<0, U>([&](auto uc) MWD_INLINE { step(uc, std::true_type{}, sb + decltype(uc)::value, cb); });
-    }
+        static_for<0, U>([&](auto uc) MWD_INLINE { step(uc, std::true_type{}, ti, sb + decltype(uc)::value, cb); });
+      }
+    };
+    // the wave's row type, if its level sets are those of an unclipped tile
+    int rtype = -1;
+    static_for<0, CR::ntypes()>([&](auto ic) MWD_INLINE {
+        constexpr int yt = CR::rep(decltype(ic)::value);
+        constexpr uint32_t CM = CR::cmask(yt), PM = CR::pmask(yt), SM = CR::smask(yt);
+        if (cmask == CM && pmask == PM && smask == SM) rtype = decltype(ic)::value;
+    });
+    rtype = __builtin_amdgcn_readfirstlane(rtype);
+    if (rtype < 0) fast_chunks(std::integral_constant<int, -1>{});
+    static_for<0, CR::ntypes()>([&](auto ic) MWD_INLINE {
+        if (rtype == decltype(ic)::value) fast_chunks(ic);
+    });
     generic_chunks(s_fast_end, s_last + 1);
 }
 

@@ -49,6 +49,8 @@ constexpr int kMinProxyNz = 64;
 // A tile kernel that spills more than this to scratch memory (bytes per lane)
 // is not tried; a few spilled registers outside the step loop cost little.
 constexpr size_t kMaxSpillBytes = 128;
+// factor on a batched MWD shape's proxy time (see tune_generic)
+constexpr double kBatchMwdPenalty = 2.0;
 
 const char* cache_path()
 {
@@ -262,7 +264,15 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, int batch, 
             for (const TuneChoice& c : cands) {
                 // a batched shape is timed through the row kernel of the same tile
                 if (c.mode == STENCIL_MODE_MWD && !mwd_supported(kind, dtype, c.shape)) continue;
-                const double ms = predict_ms(P, T, nz, c, s);
+                double ms = predict_ms(P, T, nz, c, s);
+                // The proxy times a batched MWD shape through the single-grid
+                // row kernel; in the batch the shape runs inside the shared
+                // 1024-thread kernel (fewer registers per lane) and in row
+                // groups that wait for every grid's previous row, which the
+                // proxy does not see (on 256 mixed 7c/25c grids, all grids
+                // on MWD ran 2.8x slower than all grids naive).  So in a batch
+                // MWD must win the proxy by 2x.
+                if (batch == 1 && c.mode == STENCIL_MODE_MWD && ms > 0) ms *= kBatchMwdPenalty;
                 if (verbose)
                     std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d (proxy %d planes) T=%d%s: %s dw %d lanes %d: %.3f ms\n",
                                  kind, dtype, nx, ny, nz, nzp, T, batch ? " (batched)" : "",
