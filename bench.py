@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--naive-steps", type=int, default=2)
     ap.add_argument("--no-naive", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-against-FP64 sub-run of an FP32 workload")
+    ap.add_argument("--no-energy", action="store_true",
+                    help="skip the GPU energy-to-solution measurement (AMD SMI energy counter)")
     ap.add_argument("--cpu-T", type=int, default=0, help="time steps of the oracle sample")
     ap.add_argument("--sweep", action="store_true",
                     help="also time every compiled MWD shape (diamond width x lanes)")
@@ -67,8 +71,10 @@ def make_inputs(w, dtype, windex):
     return u0, co
 
 
-def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, dw, lanes, halo):
-    """Run warmup + timed steps; return (seconds, plan description, profile)."""
+def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, dw, lanes, halo, meter=None):
+    """Run warmup + timed steps; return (seconds, plan description, profile).
+    With an energy meter, also the energy of repeated runs (outside the timed
+    steps) in desc["energy"]."""
     a = u0_dev.clone()
     b = u0_dev.clone()
     g = S.make_grid(a, b, halo, 0)
@@ -105,6 +111,21 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
     l2, mx = S.stencil_norms(g, 0)
     rl2, rmx = S.stencil_norms(g, 1)
     desc["norms"] = {"u_l2": l2, "u_max": mx, "residual_l2": rl2, "residual_max": rmx}
+    if meter is not None and meter.ok:
+        from paper_1410_5561_amd import energy
+        # three windows of repeated runs; the median window by energy per LUP
+        wins = []
+        for _ in range(3):
+            reps, dt, joules, smu_w = energy.measure(meter, lambda: plan.run(g, c, T), torch.cuda.synchronize,
+                                                     min_seconds=1.5)
+            lups = n[0] * n[1] * n[2] * T * reps
+            wins.append({"runs": reps, "seconds": round(dt, 3), "joules": round(joules, 3),
+                         "avg_power_W": round(joules / dt, 1),
+                         "firmware_avg_power_W": None if smu_w is None else round(smu_w, 1),
+                         "pJ_per_LUP": round(joules / lups * 1e12, 2),
+                         "GLUP_per_s": round(lups / dt / 1e9, 2)})
+        wins.sort(key=lambda e: e["pJ_per_LUP"])
+        desc["energy"] = dict(wins[1], pJ_per_LUP_windows=[e["pJ_per_LUP"] for e in wins])
     state = (a, b)[g.cur]
     plan.close()
     return max(ev, 1e-9), wall, desc, prof, state
@@ -286,9 +307,13 @@ def main():
         co_dev = [torch.from_numpy(c).cuda() for c in co]
     del u0
     co = None
+    meter = None
+    if not a.no_energy:
+        from paper_1410_5561_amd import energy
+        meter = energy.EnergyMeter()
     log(a, "timing MWD")
     sec, wall, desc, prof, state = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev, co_dev, T,
-                                             a.steps, a.warmup, a.mode, a.dw, a.lanes, R)
+                                             a.steps, a.warmup, a.mode, a.dw, a.lanes, R, meter=meter)
     value = a.steps * lups / sec / 1e9
     main_launches = max(1, prof["main_launches"])
     model_bpl = desc["model_bytes_per_lup"]
@@ -337,7 +362,7 @@ def main():
     if not a.no_naive and mode_name != "naive":
         log(a, "timing naive")
         nsec, _, ndesc, nprof, _ = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev, co_dev, T,
-                                             a.naive_steps, 1, "naive", 0, 0, R)
+                                             a.naive_steps, 1, "naive", 0, 0, R, meter=meter)
         nval = a.naive_steps * lups / nsec / 1e9
         nb = ndesc["model_bytes_per_lup"]
         out["naive"] = {"value": round(nval, 3), "unit": "GLUP/s",
@@ -345,6 +370,21 @@ def main():
                         "model_bytes_per_lup": nb,
                         "achieved_GBs_at_model_bytes": round(nval * nb, 1)}
         out["speedup_vs_naive"] = round(value / nval, 3)
+    if meter is not None:
+        # energy to solution of repeated whole runs (after the timed steps),
+        # from the GPU socket's energy counter
+        en = {"meter": "AMD SMI energy counter of the GPU socket"}
+        if not meter.ok:
+            en["error"] = meter.error
+        else:
+            en[mode_name] = desc.get("energy")
+            if not a.no_naive and mode_name != "naive":
+                en["naive"] = ndesc.get("energy")
+                if en[mode_name] and en["naive"]:
+                    en["energy_ratio_naive_over_%s" % mode_name] = round(
+                        en["naive"]["pJ_per_LUP"] / en[mode_name]["pJ_per_LUP"], 3)
+        out["energy"] = en
+        meter.close()
     if a.sweep:
         shapes = {1: [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
                   4: [(8, 64), (8, 128), (16, 64)]}[R]
@@ -362,7 +402,7 @@ def main():
                        "GBs_at_model": round(sv * sdesc["model_bytes_per_lup"], 1)})
             log(a, "sweep", sw[-1])
         out["sweep"] = sw
-    if dtype == "f32":
+    if dtype == "f32" and not a.no_precision:
         log(a, "precision sub-run")
         out["fp32_vs_fp64"] = precision_subrun(S, torch, w, a.workload,
                                                 n=tuple(w.get("error_subrun", (256, 256, 256))))

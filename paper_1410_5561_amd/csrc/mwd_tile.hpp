@@ -410,7 +410,6 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         static_assert(!CAN || FAST, "row types are for steady-state steps");
         constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
         const int eb = s & 1;
-        if constexpr (CAN) asm volatile("; row type %0" ::"n"(TI));
         // the wave's level sets: constants for a row type; otherwise re-read
         // at every step so that the per-level tests below stay scalar
         // compares instead of lane masks held (and spilled) across the loop

@@ -53,7 +53,12 @@ def source_hash(kernel: str) -> str:
 
 
 def _csvs(d, suffix):
-    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    """The run's file of this kind: a directory must hold exactly one run
+    (one process), so that runs of different builds are never averaged."""
+    files = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if len(files) > 1:
+        raise SystemExit("%s holds %d runs (%s files); use a fresh directory per run" % (d, len(files), suffix))
+    return files
 
 
 def kernel_durations(trace_dir, match):
