@@ -407,7 +407,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         constexpr bool FAST = decltype(fc)::value;
         constexpr int TI = decltype(ti)::value;
         constexpr bool CAN = TI >= 0;
-        static_assert(!CAN || FAST, "row types are for steady-state steps");
+        // a typed steady-state step computes every lane (see below)
+        constexpr bool UNMASKED = CAN && FAST;
         constexpr int k = u % PL;  // load slot consumed, then refilled, at this step
         const int eb = s & 1;
         // the wave's level sets: constants for a row type; otherwise re-read
@@ -450,8 +451,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         static_for<0, L>([&](auto tc) MWD_INLINE {
             constexpr int tau = decltype(tc)::value;
             const int p = s - (tau + 1) * R;
-            const bool pub = CAN ? ((pm >> tau) & 1u) != 0u
-                                 : (FAST || (((pm >> tau) & 1u) && p >= 0 && p < a.nz));
+            const bool held = ((pm >> tau) & 1u) != 0u;
+            const bool pub = FAST ? (!CAN || held) : (held && p >= 0 && p < a.nz);
             if (pub) ex[eb][tau][yr + R][xl] = q[tau][cmod(u - (tau + 1) * R, Q)];
         });
         // side row: unconditional, so the wait for its load is the same on
@@ -496,7 +497,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             });
           }
         };
-        if constexpr (!CAN) boundary();
+        if constexpr (!UNMASKED) boundary();
         // (3) stores of the previous step (its values are still in the
         //     queues): the last two levels of each point.  Issued before this
         //     step's loads, so waits on those loads stay exact.
@@ -547,8 +548,8 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             };
             const int pl = s + PL;  // level 0's plane at step s + PL
             if (sv_present) sv[k] = gld(sv_src, pl - H * R, 0, a.nz, off_s);
-            if (has_a) lea[k] = gld(srca, pl - ta * R, 0, a.nz, colb);
-            if (has_b) leb[k] = gld(srcb, pl - tb * R, 0, a.nz, colb);
+            if (hasa) lea[k] = gld(srca, pl - ta * R, 0, a.nz, colb);
+            if (hasb) leb[k] = gld(srcb, pl - tb * R, 0, a.nz, colb);
             // boundary values: at boundary planes every lane needs them, at
             // other planes the lanes outside the domain
             const bool pbnd = pl < 0 || pl >= a.nz;
@@ -572,7 +573,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         constexpr bool XYPF = R == 1 && (L <= 3 || (sizeof(T) == 4 && L <= 7));
         T xy[XYPF ? L + 1 : 1][4];
         if constexpr (XYPF) {
-            if (CAN || (xl >= R && xl < LX - R)) {
+            if (UNMASKED || (xl >= R && xl < LX - R)) {
                 static_for<1, L + 1>([&](auto tc) MWD_INLINE {
                     constexpr int tau = decltype(tc)::value;
                     xy[tau][0] = ex[eb][tau - 1][yr + R][xl + 1];
@@ -588,7 +589,7 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             if (((cm >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
                 // a row type computes every lane: a lane outside the level's
                 // x range reads in-bounds LDS and its value is never read
-                if (CAN || (xin && xl >= tau * R && xl < LX - tau * R)) {
+                if (UNMASKED || (xin && xl >= tau * R && xl < LX - tau * R)) {
                     auto nb = [&](int dx, int dy, int dz) MWD_INLINE -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
                         if constexpr (XYPF) {
@@ -613,17 +614,16 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
                 }
             }
         });
-        if constexpr (CAN) boundary();
+        if constexpr (UNMASKED) boundary();
     };
 
     const char* const nocb[1] = {nullptr};
-    auto generic_chunks = [&](int from, int to) MWD_INLINE {
+    auto generic_chunks = [&](auto ti, int from, int to) MWD_INLINE {
         for (int sb = from; sb < to; sb += U)
             static_for<0, U>([&](auto uc) MWD_INLINE {
-                step(uc, std::false_type{}, std::integral_constant<int, -1>{}, opaque_uniform(sb + decltype(uc)::value), nocb);
+                step(uc, std::false_type{}, ti, opaque_uniform(sb + decltype(uc)::value), nocb);
             });
     };
-    generic_chunks(s_first, s_fast_begin);
     auto fast_chunks = [&](auto ti) MWD_INLINE {
       for (int sb = s_fast_begin; sb < s_fast_end; sb += U) {
         const int pl = sb + PL;
@@ -641,19 +641,26 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         static_for<0, U>([&](auto uc) MWD_INLINE { step(uc, std::true_type{}, ti, sb + decltype(uc)::value, cb); });
       }
     };
-    // the wave's row type, if its level sets are those of an unclipped tile
+    auto sweep = [&](auto ti) MWD_INLINE {
+        generic_chunks(ti, s_first, s_fast_begin);
+        fast_chunks(ti);
+        generic_chunks(ti, s_fast_end, s_last + 1);
+    };
+    // the wave's row type, if its level sets are those of an unclipped tile;
+    // shapes with more than four types (Dw 16 at radius 1, whose 15 levels
+    // do not fit the registers anyway) compile the untyped sweep only
+    constexpr int NTYPES = CR::ntypes() <= 4 ? CR::ntypes() : 0;
     int rtype = -1;
-    static_for<0, CR::ntypes()>([&](auto ic) MWD_INLINE {
+    static_for<0, NTYPES>([&](auto ic) MWD_INLINE {
         constexpr int yt = CR::rep(decltype(ic)::value);
         constexpr uint32_t CM = CR::cmask(yt), PM = CR::pmask(yt), SM = CR::smask(yt);
         if (cmask == CM && pmask == PM && smask == SM) rtype = decltype(ic)::value;
     });
     rtype = __builtin_amdgcn_readfirstlane(rtype);
-    if (rtype < 0) fast_chunks(std::integral_constant<int, -1>{});
-    static_for<0, CR::ntypes()>([&](auto ic) MWD_INLINE {
-        if (rtype == decltype(ic)::value) fast_chunks(ic);
+    if (rtype < 0) sweep(std::integral_constant<int, -1>{});
+    static_for<0, NTYPES>([&](auto ic) MWD_INLINE {
+        if (rtype == decltype(ic)::value) sweep(ic);
     });
-    generic_chunks(s_fast_end, s_last + 1);
 }
 
 }  // namespace mwd
