@@ -5,9 +5,12 @@ and the DRAM's energy through RAPL).
 The meter reads the GPU's accumulated energy counter through the AMD SMI
 library (``amdsmi_get_energy_count``: an accumulator in units of
 ``counter_resolution`` microjoules, kept by the firmware for the whole
-socket).  A measurement is the difference of two readings around a region
-that ends with a device synchronisation; the counter advances in steps of
-about a millisecond, so a region should last a second or more.
+socket), which comes with the time of its last update (ns).  A measurement
+reads it before and after a region that ends with a device synchronisation;
+the counter is updated in steps, so the energy difference is divided by the
+difference of the counter's own timestamps (not by the wall time between the
+reads) to give the region's average power, and the region's energy is that
+power times its wall time.
 
     meter = EnergyMeter()          # None-safe: meter.ok tells whether it works
     j0 = meter.joules()
@@ -39,8 +42,12 @@ class EnergyMeter:
             self.error = "%s: %s" % (type(e).__name__, e)
 
     def joules(self) -> float:
+        return self.read()[0]
+
+    def read(self):
+        """(joules accumulated, seconds: the time of the counter's last update)."""
         e = self._smi.amdsmi_get_energy_count(self._h)
-        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6, e["timestamp"] * 1e-9
 
     def power_w(self):
         """The firmware's own average socket power in watts (a cross-check
@@ -67,10 +74,11 @@ class EnergyMeter:
 def measure(meter: EnergyMeter, run, sync, min_seconds: float = 2.0, max_reps: int = 1000):
     """Repeat ``run()`` until at least ``min_seconds`` have passed (after
     ``sync()``); return (repetitions, seconds, joules, mean of the firmware's
-    power readings taken at the synchronisations, or None)."""
+    power readings taken at the synchronisations, or None).  joules is the
+    counter's average power over its own update times times the wall time."""
     import time
     sync()
-    j0 = meter.joules()
+    j0, ts0 = meter.read()
     t0 = time.perf_counter()
     reps = 0
     pw = []
@@ -86,5 +94,6 @@ def measure(meter: EnergyMeter, run, sync, min_seconds: float = 2.0, max_reps: i
                 break
     sync()
     dt = time.perf_counter() - t0
-    j1 = meter.joules()
-    return reps, dt, j1 - j0, (sum(pw) / len(pw) if pw else None)
+    j1, ts1 = meter.read()
+    joules = (j1 - j0) / (ts1 - ts0) * dt if ts1 > ts0 else j1 - j0
+    return reps, dt, joules, (sum(pw) / len(pw) if pw else None)

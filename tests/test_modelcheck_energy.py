@@ -68,14 +68,17 @@ def test_table_refuses_mixed_runs(tmp_path):
 
 
 class _FakeMeter:
-    """A counter that advances 300 J per run."""
+    """A counter that advances 300 J per run and whose timestamps run at the
+    same rate as the region's wall time."""
     ok = True
 
     def __init__(self):
+        import time
         self.j = 1000.0
+        self.t = time.perf_counter
 
-    def joules(self):
-        return self.j
+    def read(self):
+        return self.j, self.t()
 
     def power_w(self):
         return 250.0
@@ -88,7 +91,32 @@ def test_energy_measure_counts_runs_and_joules():
         m.j += 300.0
 
     reps, dt, joules, pw = energy.measure(m, run, lambda: None, min_seconds=0.0, max_reps=8)
-    assert reps >= 1 and joules == pytest.approx(300.0 * reps) and pw == 250.0 and dt >= 0.0
+    # energy = (counter difference / counter time) x wall time: equal up to
+    # the few instructions between the wall clock's and the counter's reads
+    assert reps >= 1 and joules == pytest.approx(300.0 * reps, rel=0.2) and pw == 250.0 and dt >= 0.0
+
+
+class _SteppedMeter(_FakeMeter):
+    """A counter that reports a stale update time: the counter's own
+    timestamps, not the wall time between reads, give the power."""
+
+    def read(self):
+        return self.j, self.stamp
+
+    def power_w(self):
+        return None
+
+
+def test_energy_uses_counter_timestamps():
+    m = _SteppedMeter()
+    m.stamp = 10.0
+
+    def run():
+        m.j += 500.0
+        m.stamp += 1.0  # 500 J per counter second: 500 W
+
+    reps, dt, joules, pw = energy.measure(m, run, lambda: None, min_seconds=0.0, max_reps=4)
+    assert joules == pytest.approx(500.0 * dt) and pw is None
 
 
 def test_energy_meter_without_device_reports_error():
