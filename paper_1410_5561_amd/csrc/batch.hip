@@ -59,6 +59,9 @@ constexpr size_t kCacheGroupBytes = size_t(96) << 20;
 constexpr int kNaiveBranches = 2;
 // workgroups per launch below which a group's z chunks are halved
 constexpr long long kNaiveMinBlocks = 2048;
+// runs of this many consecutive naive blocks (neighbours in x and y, whose
+// halos overlap) go to one XCD: the blocks one XCD holds at once
+constexpr int kNaiveXcdRun = 64;
 
 static int variant_index(int kind, int dtype, const MwdShape& s)
 {
@@ -224,7 +227,10 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
                     for (int by = 0; by * kNaiveBY < na.ny; ++by)
                         for (int bx = 0; bx * kNaiveBX < na.nx; ++bx) ntiles.push_back(NaiveTile{i, bx, by, bz});
             }
-            ngroups.emplace_back(first, (int)ntiles.size() - first);
+            const int cnt = (int)ntiles.size() - first;
+            std::vector<NaiveTile> g(ntiles.begin() + first, ntiles.end());
+            for (int q = 0; q < cnt; ++q) ntiles[first + q] = g[xcd_tile(q, cnt, kNaiveXcdRun)];
+            ngroups.emplace_back(first, cnt);
             k = k1;
         }
     }

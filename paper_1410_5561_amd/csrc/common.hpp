@@ -89,4 +89,21 @@ struct Weights {
     const T* arr[13];
 };
 
+// Logical block of workgroup blk in a launch of ntiles blocks.  Workgroups
+// go to the eight XCDs round-robin (block i to XCD i mod 8), each XCD with
+// its own L2.  Neighbouring blocks that share cache lines (the overlapping x
+// tiles of one diamond; the x- and y-neighbours of a sweep's blocks) should
+// run on one XCD, where the second read of a shared line can hit in L2: so
+// runs of c consecutive logical blocks go to one XCD.  The last, partial
+// group of 8c blocks keeps the identity; the map is a bijection.
+__host__ __device__ __forceinline__ int xcd_tile(int blk, int ntiles, int c)
+{
+    constexpr int NXCD = 8;
+    const int gsz = NXCD * c;
+    const int g = blk / gsz;
+    if ((g + 1) * gsz > ntiles) return blk;
+    const int r = blk - g * gsz;
+    return g * gsz + (r % NXCD) * c + r / NXCD;
+}
+
 }  // namespace mwd

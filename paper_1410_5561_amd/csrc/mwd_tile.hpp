@@ -189,22 +189,6 @@ struct MwdArgs {
     int nxt;              // x tiles per diamond
 };
 
-// Tile of workgroup blk in a launch of ntiles tiles t = b * nxt + j.
-// Workgroups go to the eight XCDs round-robin (block i to XCD i mod 8), each
-// XCD with its own L2.  The x tiles of one diamond overlap by 2LR columns and
-// share the cache lines at their ends, so runs of c consecutive tiles go to
-// one XCD, where the second read of a shared line can hit in L2.  The last,
-// partial group of 8c tiles keeps the identity; the map is a bijection.
-__host__ __device__ __forceinline__ int xcd_tile(int blk, int ntiles, int c)
-{
-    constexpr int NXCD = 8;
-    const int gsz = NXCD * c;
-    const int g = blk / gsz;
-    if ((g + 1) * gsz > ntiles) return blk;
-    const int r = blk - g * gsz;
-    return g * gsz + (r % NXCD) * c + r / NXCD;
-}
-
 // One diamond row of the schedule.
 struct MwdRow {
     int rho, t0;          // row index and the level just below the row's tiles

@@ -1,16 +1,24 @@
 // The naive sweep: one launch per time step over the whole grid.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "naive_block.hpp"
 
 namespace mwd {
 
+// One-dimensional grid over the blocks (bx fastest, then by, then bz).  Runs
+// of `patch` consecutive blocks (whole block rows) go to one XCD, so that a
+// block's x- and y-neighbours, whose halo rows and partial cache lines it
+// reads, mostly run at the same time on the same L2.
 template <int K, typename T, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY)
 naive_sweep_kernel(const T* __restrict__ src, T* __restrict__ dst, Weights<T> w,
-                   int nx, int ny, int nz, long long sy, long long sz, int zchunk)
+                   int nx, int ny, int nz, long long sy, long long sz, int zchunk, int nbx, int nby, int patch)
 {
     __shared__ T tile[BY + 2 * KindTraits<K>::R][BX + 2 * KindTraits<K>::R];
-    naive_block<K, T, BX, BY>(src, dst, w, nx, ny, nz, sy, sz, zchunk, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+    const int t = xcd_tile(blockIdx.x, gridDim.x, patch);
+    const int r = t / nbx;
+    naive_block<K, T, BX, BY>(src, dst, w, nx, ny, nz, sy, sz, zchunk, t - r * nbx, r % nby, r / nby, tile);
 }
 
 template <int K, typename T>
@@ -26,10 +34,16 @@ static hipError_t launch_naive(const DevGrid& g, const HostWeights& hw, const vo
         w.arr[m] = static_cast<const T*>(hw.org[m]);
     }
     const int zchunk = (R == 1) ? 64 : 128;
-    dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + zchunk - 1) / zchunk);
-    hipLaunchKernelGGL((naive_sweep_kernel<K, T, BX, BY>), grid, dim3(BX * BY), 0, stream,
+    const long long nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY, nbz = (g.nz + zchunk - 1) / zchunk;
+    const long long nblocks = nbx * nby * nbz;
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    // about as many blocks per patch as one XCD (32 CUs) holds at once: two
+    // 1024-thread blocks or four 512-thread blocks per CU
+    const int resident = 32 * ((BX * BY) <= 512 ? 4 : 2);
+    const int patch = (int)(nbx * std::max<long long>(1, std::min<long long>(nby, resident / nbx)));
+    hipLaunchKernelGGL((naive_sweep_kernel<K, T, BX, BY>), dim3((unsigned)nblocks), dim3(BX * BY), 0, stream,
                        static_cast<const T*>(src), static_cast<T*>(dst), w,
-                       g.nx, g.ny, g.nz, g.sy, g.sz, zchunk);
+                       g.nx, g.ny, g.nz, g.sy, g.sz, zchunk, (int)nbx, (int)nby, patch);
     return hipGetLastError();
 }
 
