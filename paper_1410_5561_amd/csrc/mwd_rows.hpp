@@ -3,31 +3,19 @@
 // kernel instantiations compile in parallel.
 #pragma once
 
-#include <algorithm>
-
 #include "internal.hpp"
 #include "mwd_tile.hpp"
 
 namespace mwd {
 
-// One launch: diamonds [d0[0], d0[0] + n[0]) of row r[0], then diamonds
-// [d0[1], d0[1] + n[1]) of row r[1] (n[1] may be 0), every x tile of each.
-struct MwdBand {
-    MwdRow r[2];
-    int d0[2], n[2];
-};
-
 template <int K, typename T, int DW, int WPR>
 __global__ void __launch_bounds__(64 * DW * WPR)
-mwd_row_kernel(MwdArgs<T> a, MwdBand band)
+mwd_row_kernel(MwdArgs<T> a, MwdRow row)
 {
     using G = MwdGeom<K, DW, WPR>;
     __shared__ T ex[2][G::L][G::NSX][G::LX];
-    int t = xcd_tile(blockIdx.x, gridDim.x, a.nxt);
-    const int n0 = band.n[0] * a.nxt;
-    const int s = t < n0 ? 0 : 1;
-    t -= s * n0;
-    mwd_tile<K, T, DW, WPR>(a, band.r[s], band.d0[s] + t / a.nxt, t % a.nxt, ex);
+    const int t = xcd_tile(blockIdx.x, gridDim.x, a.nxt);
+    mwd_tile<K, T, DW, WPR>(a, row, t / a.nxt, t % a.nxt, ex);
 }
 
 // After the last row, copy u_T and u_{T-1} of every point out of the pair
@@ -104,66 +92,15 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    auto row_of_rho = [&](int rho) {
+    for (int rho = rho_lo; rho <= rho_hi; ++rho) {
         MwdRow row;
         row.rho = rho;
         row.t0 = (rho - 1) * G::H;
         const int yoff = (rho % 2) * (DW / 2);
         row.ybase = yoff > 0 ? yoff - DW : 0;
-        return row;
-    };
-    auto diamonds = [&](const MwdRow& row) { return (g.ny - 1 - row.ybase) / DW + 1; };
-    // Workgroups the GPU holds at once.  A row whose tiles need more than
-    // that runs in launches of whole rounds (m rounds: at most m * slots
-    // tiles each), and the launch that ends a row also starts the next row
-    // with the diamonds that need nothing from this launch: next-row diamond
-    // e reads rows [yL' - R, yL' + Dw + R) and writes [yL', yL' + Dw), this
-    // launch's part of the row, from diamond D on, reads from yL(D) - R and
-    // writes from yL(D), and the next row writes the pair this row reads, so
-    // yL'(e) + Dw + R <= yL(D) keeps the two parts apart.  That removes most
-    // of the partly filled last round of every row.
-    int slots = 0;
-    {
-        int dev = 0, ncu = 0, per = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per, reinterpret_cast<const void*>(&mwd_row_kernel<K, T, DW, WPR>), G::NT, 0) == hipSuccess)
-            slots = ncu * per;
-        (void)hipGetLastError();
-    }
-    int rho = rho_lo, d = 0;
-    while (rho <= rho_hi) {
-        const MwdRow row = row_of_rho(rho);
-        const int nb = diamonds(row);
-        int cap = nb;
-        if (slots > 0 && (long long)nb * a.nxt > slots) {
-            const long long m = (long long)nb * a.nxt / slots;
-            cap = (int)std::max(1LL, m * slots / a.nxt);
-        }
-        MwdBand band;
-        band.r[0] = row;
-        band.d0[0] = d;
-        band.n[0] = std::min(cap, nb - d);
-        band.r[1] = row;
-        band.d0[1] = 0;
-        band.n[1] = 0;
-        const int D = d;
-        d += band.n[0];
-        if (d >= nb) {
-            if (rho + 1 <= rho_hi && D > 0) {
-                const MwdRow next = row_of_rho(rho + 1);
-                // next-row diamonds e = 0 .. E-1 with yL'(e) + Dw + R <= yL(D)
-                const int E = floordiv(row.ybase + D * DW - DW - G::R - next.ybase, DW) + 1;
-                band.r[1] = next;
-                band.n[1] = std::max(0, std::min({cap - band.n[0], E, diamonds(next)}));
-            }
-            ++rho;
-            d = band.n[1];
-        }
-        const int ntiles = (band.n[0] + band.n[1]) * a.nxt;
+        const int nB = (g.ny - 1 - row.ybase) / DW + 1;
         if (prof) prof->begin(stream);
-        hipLaunchKernelGGL((mwd_row_kernel<K, T, DW, WPR>), dim3(ntiles), dim3(G::NT), 0, stream, a, band);
+        hipLaunchKernelGGL((mwd_row_kernel<K, T, DW, WPR>), dim3(nB * a.nxt), dim3(G::NT), 0, stream, a, row);
         if (prof) prof->end(stream, 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -83,50 +83,8 @@ def _apply(kind, nb, w):
     return u
 
 
-def row_params(rho, H, DW):
-    """(t0, ybase) of diamond row rho."""
-    yoff = (rho % 2) * (DW // 2)
-    return (rho - 1) * H, (yoff - DW if yoff > 0 else 0)
-
-
-def band_schedule(ny, DW, R, H, nxt, rho_max, slots):
-    """The library's launches: each a list of (rho, diamond).  A row whose
-    tiles exceed ``slots`` runs in launches of whole rounds, and the launch
-    that ends a row starts the next row with the diamonds e whose rows
-    [yL'(e) - R, yL'(e) + DW + R) stay below yL(D) of this launch's part of
-    the row (the rule the row scheduler states)."""
-    def nb_of(rho):
-        return (ny - 1 - row_params(rho, H, DW)[1]) // DW + 1
-
-    out = []
-    rho, d = 0, 0
-    while rho <= rho_max:
-        nb = nb_of(rho)
-        cap = nb
-        if slots and nb * nxt > slots:
-            cap = max(1, (nb * nxt // slots) * slots // nxt)
-        n0 = min(cap, nb - d)
-        launch = [(rho, b) for b in range(d, d + n0)]
-        D = d
-        d += n0
-        if d >= nb:
-            n1 = 0
-            if rho + 1 <= rho_max and D > 0:
-                yb, ybn = row_params(rho, H, DW)[1], row_params(rho + 1, H, DW)[1]
-                E = floordiv(yb + D * DW - DW - R - ybn, DW) + 1
-                n1 = max(0, min(cap - n0, E, nb_of(rho + 1)))
-                launch += [(rho + 1, b) for b in range(n1)]
-            rho += 1
-            d = n1
-        out.append(launch)
-    return out
-
-
-def simulate(kind, u0, coeffs, T, DW, LX, halo=None, cur=0, shuffle_seed=None, checks=True, slots=None):
-    """Run the MWD schedule on the CPU; returns (buf0, buf1, new_cur).
-    With ``slots``, tiles run in the library's banded launches (a launch may
-    hold the end of one row and the start of the next), and the concurrency
-    checks apply per launch."""
+def simulate(kind, u0, coeffs, T, DW, LX, halo=None, cur=0, shuffle_seed=None, checks=True):
+    """Run the MWD schedule on the CPU; returns (buf0, buf1, new_cur)."""
     R = RADIUS[kind]
     h = R if halo is None else halo
     dt = u0.dtype
@@ -148,19 +106,17 @@ def simulate(kind, u0, coeffs, T, DW, LX, halo=None, cur=0, shuffle_seed=None, c
     rng = np.random.default_rng(shuffle_seed) if shuffle_seed is not None else None
     zs_all = np.arange(-R, nz + R)  # plane index space of the value arrays
 
-    if slots:
-        launches = band_schedule(ny, DW, R, H, nxt, rho_max, slots)
-    else:
-        launches = [[(rho, b) for b in range((ny - 1 - row_params(rho, H, DW)[1]) // DW + 1)]
-                    for rho in range(rho_max + 1)]
-    for launch in launches:
-        tiles = [(rho, b, j) for (rho, b) in launch for j in range(nxt)]
+    for rho in range(rho_max + 1):
+        t0 = (rho - 1) * H
+        yoff = (rho % 2) * (DW // 2)
+        ybase = yoff - DW if yoff > 0 else 0
+        nB = (ny - 1 - ybase) // DW + 1
+        tiles = [(b, j) for b in range(nB) for j in range(nxt)]
         if rng is not None:
             rng.shuffle(tiles)
         reads = [[np.zeros(u0.shape, bool) for _ in range(2)] for _ in range(3)]
         owner = [[np.full(u0.shape, -1, np.int64) for _ in range(2)] for _ in range(3)]
-        for (rho, b, j) in tiles:
-            t0, ybase = row_params(rho, H, DW)
+        for (b, j) in tiles:
             yL = ybase + b * DW
             x0 = j * XT
             xs = x0 - L * R + np.arange(LX)
@@ -251,14 +207,13 @@ def simulate(kind, u0, coeffs, T, DW, LX, halo=None, cur=0, shuffle_seed=None, c
                     assert not np.isnan(vv).any(), "stored an unset value (row %d tile %s)" % (rho, (b, j))
                     own = owner[pr][bi][h:h + nz, y + h, xs[ko] + h]
                     assert (own < 0).all(), "two tiles write the same points (row %d)" % rho
-                    owner[pr][bi][h:h + nz, y + h, xs[ko] + h] = (rho * 1000 + b) * 1000 + j
+                    owner[pr][bi][h:h + nz, y + h, xs[ko] + h] = b * 100000 + j
                     bufs.p[pr][bi][h:h + nz, y + h, xs[ko] + h] = vv
         if checks:
             for pp in range(3):
                 for bb in range(2):
                     clash = reads[pp][bb] & (owner[pp][bb] >= 0)
-                    assert not clash.any(), "a launch reads points it writes (rows %s, pair %d)" % (
-                        sorted({r for r, _ in launch}), pp)
+                    assert not clash.any(), "row %d reads points it writes (pair %d)" % (rho, pp)
     # gather u_T and u_{T-1} into pair 0
     for k in (0, 1):
         t = T - k

@@ -99,11 +99,11 @@ def test_mwd_bitexact_steady_state(case):
                                   ("7c", np.float32, 8, 64, (512, 400, 16), 10),
                                   ("25c", np.float64, 16, 64, (512, 400, 20), 8)],
                          ids=lambda c: "%s-%s-dw%d-%s" % (c[0], np.dtype(c[1]).name, c[2], "x".join(map(str, c[4]))))
-def test_mwd_banded_launches(case):
-    """Rows with more tiles than the GPU holds at once: launches of whole
-    rounds that hold the end of one diamond row and the start of the next."""
+def test_mwd_rows_larger_than_the_gpu(case):
+    """Diamond rows with more tiles than the GPU holds at once (several
+    rounds of workgroups per row launch)."""
     kind, dtype, dw, lanes, n, T = case
-    print("mwd banded", kind, np.dtype(dtype).name, dw, lanes, n, T, flush=True)
+    print("mwd large rows", kind, np.dtype(dtype).name, dw, lanes, n, T, flush=True)
     u0, co = _inputs(kind, n, dtype, seed=31)
     got = run_gpu(kind, u0, co, T, mode="mwd", dw=dw, lanes=lanes)
     _check(kind, u0, co, T, *got)

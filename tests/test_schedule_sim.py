@@ -55,59 +55,6 @@ def test_schedule_matches_oracle(case, dtype):
         assert np.array_equal(bufs[ncur ^ 1], uTm1)
 
 
-BAND_CASES = [
-    # kind, DW, LX, (nx, ny, nz), T, slots (workgroups resident at once)
-    ("7c", 4, 64, (20, 41, 5), 13, 3),
-    ("7c", 8, 64, (60, 70, 4), 17, 5),
-    ("7c", 8, 64, (60, 70, 4), 17, 4),
-    ("7v", 8, 64, (30, 57, 5), 12, 3),
-    ("7c", 4, 64, (70, 33, 4), 9, 7),
-    ("25c", 16, 64, (45, 70, 9), 6, 3),
-    ("7c", 8, 64, (23, 29, 7), 9, 3),
-]
-
-
-@pytest.mark.parametrize("case", BAND_CASES, ids=lambda c: "%s-dw%d-%s-T%d-s%d" % (c[0], c[1], "x".join(map(str, c[3])), c[4], c[5]))
-def test_banded_launches_match_oracle(case):
-    """Launches that hold the end of one diamond row and the start of the
-    next (sized to whole rounds of resident workgroups): no launch reads what
-    it writes, every value a tile reads was written by an earlier launch, and
-    the result is the oracle's."""
-    kind, DW, LX, n, T, slots = case
-    R = gridgen.RADIUS[kind]
-    H = DW // (2 * R)
-    XT = LX - 2 * (2 * H - 1) * R
-    nxt = -(-n[0] // XT)
-    launches = mwd_sim.band_schedule(n[1], DW, R, H, nxt, -(-T // H), slots)
-    assert any(len({r for r, _ in l}) == 2 for l in launches), "the case does not mix rows"
-    for l in launches:
-        # whole rounds: at most floor(row tiles / slots) * slots tiles
-        nb = (n[1] - 1 - mwd_sim.row_params(l[0][0], H, DW)[1]) // DW + 1
-        assert len(l) * nxt <= max(nb * nxt // slots, 1) * slots or len(l) <= 1
-    u0 = gridgen.field(23, *n, R, -1.0, 1.0, np.float64)
-    co = gridgen.C7 if kind == "7c" else gridgen.C25 if kind == "25c" else gridgen.coeffs_7v(23, *n, R)
-    b0, b1, ncur = mwd_sim.simulate(kind, u0, co, T, DW, LX, shuffle_seed=slots, slots=slots)
-    uT, uTm1 = oracle.run(kind, u0, co, T)
-    assert np.array_equal((b0, b1)[ncur], uT) and np.array_equal((b0, b1)[ncur ^ 1], uTm1)
-
-
-def test_band_schedule_covers_every_tile_once_in_row_order():
-    for ny, DW, R, nxt, T, slots in ((512, 8, 1, 11, 64, 256), (512, 16, 4, 3, 32, 256),
-                                     (1024, 8, 1, 21, 100, 256), (300, 4, 1, 5, 20, 17)):
-        H = DW // (2 * R)
-        rho_max = -(-T // H)
-        launches = mwd_sim.band_schedule(ny, DW, R, H, nxt, rho_max, slots)
-        seen = [t for l in launches for t in l]
-        want = [(rho, b) for rho in range(rho_max + 1)
-                for b in range((ny - 1 - mwd_sim.row_params(rho, H, DW)[1]) // DW + 1)]
-        assert sorted(seen) == sorted(want) and len(seen) == len(want)
-        for l in launches:
-            rows = sorted({r for r, _ in l})
-            assert len(rows) <= 2 and (len(rows) == 1 or rows[1] == rows[0] + 1)
-            nb = (ny - 1 - mwd_sim.row_params(rows[0], H, DW)[1]) // DW + 1
-            assert len(l) * nxt <= max(nb * nxt // slots, 1) * slots or len(l) <= 1
-
-
 def test_every_point_in_exactly_one_tile():
     """The diamond rows partition space-time: each (y, t), 1 <= t <= T, is
     computed by exactly one (row, diamond) and rows increase with t."""
