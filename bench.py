@@ -115,9 +115,11 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
         from paper_1410_5561_amd import energy
         # three windows of repeated runs; the median window by energy per LUP
         wins = []
+        clk = []
         for _ in range(3):
             reps, dt, joules, smu_w = energy.measure(meter, lambda: plan.run(g, c, T), torch.cuda.synchronize,
-                                                     min_seconds=1.5)
+                                                     min_seconds=1.5,
+                                                     on_sync=lambda: clk.append(meter.clocks_mhz()))
             lups = n[0] * n[1] * n[2] * T * reps
             wins.append({"runs": reps, "seconds": round(dt, 3), "joules": round(joules, 3),
                          "avg_power_W": round(joules / dt, 1),
@@ -126,6 +128,11 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
                          "GLUP_per_s": round(lups / dt / 1e9, 2)})
         wins.sort(key=lambda e: e["pJ_per_LUP"])
         desc["energy"] = dict(wins[1], pJ_per_LUP_windows=[e["pJ_per_LUP"] for e in wins])
+        clk = [c for c in clk if c]
+        if clk:
+            # clocks read at the windows' synchronisations, while the runs load the GPU
+            desc["energy"]["sclk_MHz"] = round(sum(c["sclk"] for c in clk) / len(clk))
+            desc["energy"]["mclk_MHz"] = round(sum(c["mclk"] for c in clk) / len(clk))
     state = (a, b)[g.cur]
     plan.close()
     return max(ev, 1e-9), wall, desc, prof, state

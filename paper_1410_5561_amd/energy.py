@@ -62,6 +62,18 @@ class EnergyMeter:
             pass
         return None
 
+    def clocks_mhz(self):
+        """Current graphics (SYS) and memory clocks in MHz, or None."""
+        try:
+            t = self._smi.AmdSmiClkType
+            sclk = self._smi.amdsmi_get_clock_info(self._h, t.SYS).get("clk")
+            mclk = self._smi.amdsmi_get_clock_info(self._h, t.MEM).get("clk")
+            if isinstance(sclk, (int, float)) and isinstance(mclk, (int, float)):
+                return {"sclk": sclk, "mclk": mclk}
+        except Exception:
+            pass
+        return None
+
     def close(self):
         if self._smi is not None:
             try:
@@ -71,11 +83,12 @@ class EnergyMeter:
             self._smi = None
 
 
-def measure(meter: EnergyMeter, run, sync, min_seconds: float = 2.0, max_reps: int = 1000):
+def measure(meter: EnergyMeter, run, sync, min_seconds: float = 2.0, max_reps: int = 1000, on_sync=None):
     """Repeat ``run()`` until at least ``min_seconds`` have passed (after
     ``sync()``); return (repetitions, seconds, joules, mean of the firmware's
     power readings taken at the synchronisations, or None).  joules is the
-    counter's average power over its own update times times the wall time."""
+    counter's average power over its own update times times the wall time.
+    ``on_sync()``, if given, runs at each of those synchronisations."""
     import time
     sync()
     j0, ts0 = meter.read()
@@ -90,6 +103,8 @@ def measure(meter: EnergyMeter, run, sync, min_seconds: float = 2.0, max_reps: i
             p = meter.power_w()
             if p is not None:
                 pw.append(p)
+            if on_sync is not None:
+                on_sync()
             if time.perf_counter() - t0 >= min_seconds or reps >= max_reps:
                 break
     sync()
