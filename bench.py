@@ -288,8 +288,8 @@ def bench_batch(a, torch, S):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported "
-                                   "(the multi-GPU design is described in DESIGN.md)" % a.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus %d is not supported "
+                                   "(the stencil path has no multi-GPU form)" % a.gpus}))
         return 2
     import torch
 

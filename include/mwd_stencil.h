@@ -38,7 +38,7 @@ extern "C" {
 
 #define STENCIL_OK            0
 #define STENCIL_EINVAL       -1  /* bad pointer, size, stride, halo, T, kind or dtype   */
-#define STENCIL_EUNSUPPORTED -2  /* valid request that this build cannot run           */
+#define STENCIL_EUNSUPPORTED -2  /* valid request the compiled library cannot run     */
 #define STENCIL_ENOMEM       -3  /* a device or host allocation failed                 */
 #define STENCIL_EDEVICE      -4  /* a HIP runtime call failed (text in last_error)     */
 
