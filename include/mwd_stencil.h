@@ -134,14 +134,17 @@ int stencil_destroy(stencil_plan *plan);
 /* Advance n independent grids (1 <= n <= 65535; uneven sizes, any kind; one
  * dtype per call) by T steps with ONE hipGraph launch (batched form of the
  * MWD method, Sec. II-A).  Per grid the plan picks, by kind and size bucket
- * (autotuned once), either:
+ * (autotuned once; a batched MWD shape must beat the naive sweep by 2x on its
+ * single-grid proxy, which does not see the batch's shared kernel and row
+ * groups), either:
  *  - MWD tiles: the tiles of all such grids are grouped by diamond row, one
  *    kernel launch per group (a workgroup per tile, any grid), then a gather;
  *    kernel boundaries are the row-to-row dependencies.  Shapes: 7c and 25c
  *    in both dtypes, 7v in FP32 (those compiled into the batched kernel);
  *  - the naive sweep: grids grouped so that a group's arrays fit the GPU's
  *    last-level cache, each group taking its T one-step launches before the
- *    next group starts; groups alternate between two concurrent branches.
+ *    next group starts; groups alternate between two concurrent branches;
+ *    within a group, runs of neighbouring blocks go to one XCD.
  * No workgroup waits on another.  The first call for a given set of grids
  * builds the tables, allocates scratch (two extra buffer pairs per MWD grid)
  * and captures the graph; later calls with the same grids (same pointers,
