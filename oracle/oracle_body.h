@@ -6,10 +6,11 @@
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
  * call this file.
  *
- * Every update below is the per-point expression of the paper's listings,
- * written in the listing's left-to-right C order, so that each '*' and '+' is
- * one correctly rounded IEEE operation (the file is compiled with
- * -ffp-contract=off and without -ffast-math):
+ * Every update below evaluates the per-point expression of the paper's
+ * listings term by term, from tables of neighbour offsets, in the listing's
+ * left-to-right C order, so that each '*' and '+' is one correctly rounded
+ * IEEE operation (the file is compiled with -ffp-contract=off and without
+ * -ffast-math):
  *   7-point constant coefficient   : Listing 1 (Sec. I-A)
  *   7-point variable coefficient   : Listing 2 (Sec. I-A)
  *   25-point, radius 4, 13 weights : Listing 3 (Sec. I-A); the constant form
@@ -26,6 +27,10 @@ static void SWEEP_NAME(int kind, int nx, int ny, int nz, int h,
                        const REAL *V, REAL *U,
                        const REAL *c, const REAL *const *C, int nthreads)
 {
+    /* Element stride of one step along x, y and z. */
+    const long long axis_step[3] = {1, sy, sz};
+    /* Neighbour of each radius-1 variable weight C1..C6: +x, -x, +y, -y, +z, -z. */
+    const long long nb7[6] = {1, -1, sy, -sy, sz, -sz};
     /* The listings loop k=1..N-2 (radius 1) and k=4..N-5 (radius 4) over an
      * array whose extent N includes the halo; here the interior is
      * [h, h+n) on every axis and the halo is at least the radius. */
@@ -34,53 +39,34 @@ static void SWEEP_NAME(int kind, int nx, int ny, int nz, int h,
     for (k = h; k < h + nz; k++) {
         for (int j = h; j < h + ny; j++) {
             for (int i = h; i < h + nx; i++) {
+                const long long o = (long long)k * sz + (long long)j * sy + i;
+                const REAL *v = V + o;   /* v[d]: the neighbour at element offset d */
                 REAL u;
                 if (kind == ORACLE_7C) {
-                    /* Listing 1 */
-                    u = c[0] * AT(V, k, j, i)
-                      + c[1] * (AT(V, k, j, i + 1) + AT(V, k, j, i - 1))
-                      + c[1] * (AT(V, k, j + 1, i) + AT(V, k, j - 1, i))
-                      + c[1] * (AT(V, k + 1, j, i) + AT(V, k - 1, j, i));
+                    /* Listing 1: c0 at the centre, then c1 on the neighbour
+                     * pair of each axis x, y, z, + side first */
+                    u = c[0] * v[0];
+                    for (int a = 0; a < 3; a++)
+                        u = u + c[1] * (v[axis_step[a]] + v[-axis_step[a]]);
                 } else if (kind == ORACLE_7V) {
-                    /* Listing 2: C1..C6 weight +x, -x, +y, -y, +z, -z */
-                    u = AT(C[0], k, j, i) * AT(V, k, j, i)
-                      + AT(C[1], k, j, i) * AT(V, k, j, i + 1)
-                      + AT(C[2], k, j, i) * AT(V, k, j, i - 1)
-                      + AT(C[3], k, j, i) * AT(V, k, j + 1, i)
-                      + AT(C[4], k, j, i) * AT(V, k, j - 1, i)
-                      + AT(C[5], k, j, i) * AT(V, k + 1, j, i)
-                      + AT(C[6], k, j, i) * AT(V, k - 1, j, i);
-                } else if (kind == ORACLE_25C) {
-                    /* Listing 3 with every weight constant: c[0]=C00 and
-                     * c[1..12]=C01..C12, radius-major, axis x, y, z. */
-                    u = c[0] * AT(V, k, j, i)
-                      + c[1] * (AT(V, k, j, i + 1) + AT(V, k, j, i - 1))
-                      + c[2] * (AT(V, k, j + 1, i) + AT(V, k, j - 1, i))
-                      + c[3] * (AT(V, k + 1, j, i) + AT(V, k - 1, j, i))
-                      + c[4] * (AT(V, k, j, i + 2) + AT(V, k, j, i - 2))
-                      + c[5] * (AT(V, k, j + 2, i) + AT(V, k, j - 2, i))
-                      + c[6] * (AT(V, k + 2, j, i) + AT(V, k - 2, j, i))
-                      + c[7] * (AT(V, k, j, i + 3) + AT(V, k, j, i - 3))
-                      + c[8] * (AT(V, k, j + 3, i) + AT(V, k, j - 3, i))
-                      + c[9] * (AT(V, k + 3, j, i) + AT(V, k - 3, j, i))
-                      + c[10] * (AT(V, k, j, i + 4) + AT(V, k, j, i - 4))
-                      + c[11] * (AT(V, k, j + 4, i) + AT(V, k, j - 4, i))
-                      + c[12] * (AT(V, k + 4, j, i) + AT(V, k - 4, j, i));
+                    /* Listing 2: array C0 at the centre, C1..C6 each on one
+                     * neighbour, in the order of nb7 */
+                    u = C[0][o] * v[0];
+                    for (int m = 1; m <= 6; m++)
+                        u = u + C[m][o] * v[nb7[m - 1]];
                 } else {
-                    /* Listing 3 as printed: 13 coefficient arrays */
-                    u = AT(C[0], k, j, i) * AT(V, k, j, i)
-                      + AT(C[1], k, j, i) * (AT(V, k, j, i + 1) + AT(V, k, j, i - 1))
-                      + AT(C[2], k, j, i) * (AT(V, k, j + 1, i) + AT(V, k, j - 1, i))
-                      + AT(C[3], k, j, i) * (AT(V, k + 1, j, i) + AT(V, k - 1, j, i))
-                      + AT(C[4], k, j, i) * (AT(V, k, j, i + 2) + AT(V, k, j, i - 2))
-                      + AT(C[5], k, j, i) * (AT(V, k, j + 2, i) + AT(V, k, j - 2, i))
-                      + AT(C[6], k, j, i) * (AT(V, k + 2, j, i) + AT(V, k - 2, j, i))
-                      + AT(C[7], k, j, i) * (AT(V, k, j, i + 3) + AT(V, k, j, i - 3))
-                      + AT(C[8], k, j, i) * (AT(V, k, j + 3, i) + AT(V, k, j - 3, i))
-                      + AT(C[9], k, j, i) * (AT(V, k + 3, j, i) + AT(V, k - 3, j, i))
-                      + AT(C[10], k, j, i) * (AT(V, k, j, i + 4) + AT(V, k, j, i - 4))
-                      + AT(C[11], k, j, i) * (AT(V, k, j + 4, i) + AT(V, k, j - 4, i))
-                      + AT(C[12], k, j, i) * (AT(V, k + 4, j, i) + AT(V, k - 4, j, i));
+                    /* Listing 3: weight 0 at the centre, then weight
+                     * 3(r-1)+a+1 on the pair at distance r along axis a,
+                     * radius-major and axis x, y, z inner, + side first; the
+                     * constant form holds each of the 13 weights fixed */
+                    u = (kind == ORACLE_25C ? c[0] : C[0][o]) * v[0];
+                    for (int r = 1; r <= 4; r++) {
+                        for (int a = 0; a < 3; a++) {
+                            const int q = 3 * (r - 1) + a + 1;
+                            const REAL w = kind == ORACLE_25C ? c[q] : C[q][o];
+                            u = u + w * (v[r * axis_step[a]] + v[-r * axis_step[a]]);
+                        }
+                    }
                 }
                 AT(U, k, j, i) = u;
             }

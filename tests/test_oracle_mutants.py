@@ -13,26 +13,26 @@ import oracle
 import oracle_pins as P
 
 MUTANTS = {
-    "7c_wrong_index": ("+ c[1] * (AT(V, k, j, i + 1) + AT(V, k, j, i - 1))",
-                       "+ c[1] * (AT(V, k, j, i + 1) + AT(V, k, j, i + 1))"),
-    "7c_dropped_z_pair": ("+ c[1] * (AT(V, k + 1, j, i) + AT(V, k - 1, j, i));",
-                          ";"),
-    "7c_wrong_centre_weight": ("u = c[0] * AT(V, k, j, i)\n                      + c[1]",
-                               "u = c[1] * AT(V, k, j, i)\n                      + c[1]"),
-    "7v_transposed_axis": ("+ AT(C[3], k, j, i) * AT(V, k, j + 1, i)",
-                           "+ AT(C[3], k, j, i) * AT(V, k + 1, j, i)"),
-    "7v_wrong_sign": ("+ AT(C[6], k, j, i) * AT(V, k - 1, j, i);",
-                      "- AT(C[6], k, j, i) * AT(V, k - 1, j, i);"),
-    "7v_swapped_weights": ("+ AT(C[1], k, j, i) * AT(V, k, j, i + 1)\n                      + AT(C[2], k, j, i) * AT(V, k, j, i - 1)",
-                           "+ AT(C[2], k, j, i) * AT(V, k, j, i + 1)\n                      + AT(C[1], k, j, i) * AT(V, k, j, i - 1)"),
-    "25c_wrong_radius": ("+ c[8] * (AT(V, k, j + 3, i) + AT(V, k, j - 3, i))",
-                         "+ c[8] * (AT(V, k, j + 2, i) + AT(V, k, j - 3, i))"),
-    "25c_transposed_weight": ("+ c[10] * (AT(V, k, j, i + 4) + AT(V, k, j, i - 4))\n                      + c[11]",
-                              "+ c[11] * (AT(V, k, j, i + 4) + AT(V, k, j, i - 4))\n                      + c[10]"),
-    "25v_wrong_offset": ("AT(C[12], k, j, i) * (AT(V, k + 4, j, i) + AT(V, k - 4, j, i))",
-                         "AT(C[12], k, j, i) * (AT(V, k + 4, j, i) + AT(V, k + 4, j, i))"),
-    "25v_dropped_term": ("+ AT(C[5], k, j, i) * (AT(V, k, j + 2, i) + AT(V, k, j - 2, i))",
-                         ""),
+    "7c_wrong_index": ("u = u + c[1] * (v[axis_step[a]] + v[-axis_step[a]]);",
+                       "u = u + c[1] * (v[axis_step[a]] + v[axis_step[a]]);"),
+    "7c_dropped_z_pair": ("for (int a = 0; a < 3; a++)\n                        u = u + c[1]",
+                          "for (int a = 0; a < 2; a++)\n                        u = u + c[1]"),
+    "7c_wrong_centre_weight": ("u = c[0] * v[0];", "u = c[1] * v[0];"),
+    "7v_transposed_axis": ("const long long nb7[6] = {1, -1, sy, -sy, sz, -sz};",
+                           "const long long nb7[6] = {1, -1, sz, -sy, sy, -sz};"),
+    "7v_wrong_sign": ("u = u + C[m][o] * v[nb7[m - 1]];",
+                      "u = u + (m == 6 ? -C[m][o] : C[m][o]) * v[nb7[m - 1]];"),
+    "7v_swapped_weights": ("const long long nb7[6] = {1, -1, sy, -sy, sz, -sz};",
+                           "const long long nb7[6] = {-1, 1, sy, -sy, sz, -sz};"),
+    "25_wrong_radius": ("u = u + w * (v[r * axis_step[a]] + v[-r * axis_step[a]]);",
+                        "u = u + w * (v[r * axis_step[a]] + v[-(r == 3 ? 2 : r) * axis_step[a]]);"),
+    "25_transposed_weight": ("const int q = 3 * (r - 1) + a + 1;", "const int q = 4 * a + r;"),
+    "25_wrong_offset": ("u = u + w * (v[r * axis_step[a]] + v[-r * axis_step[a]]);",
+                        "u = u + w * (v[r * axis_step[a]] + v[r * axis_step[a]]);"),
+    "25_dropped_radius": ("for (int r = 1; r <= 4; r++)", "for (int r = 1; r <= 3; r++)"),
+    "25v_constant_weight": ("const REAL w = kind == ORACLE_25C ? c[q] : C[q][o];",
+                            "const REAL w = kind == ORACLE_25C ? c[q] : C[q][0];"),
+    "7v_weight_at_wrong_point": ("u = C[0][o] * v[0];", "u = C[0][o + 1] * v[0];"),
     "no_buffer_swap": ("const REAL *V = (t % 2 == 0) ? buf0 : buf1;",
                        "const REAL *V = buf0;"),
     "short_x_loop": ("for (int i = h; i < h + nx; i++)", "for (int i = h; i < h + nx - 1; i++)"),
