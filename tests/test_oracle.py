@@ -234,3 +234,19 @@ def test_models_consistent(Dw, ND):
     for R in (1, 2, 4):
         for s in (4, 8):
             assert math.isclose(models.code_balance(Dw, ND, R, s), 2 * s * R * (ND + 2) / Dw)
+
+
+def test_model_radius4_golden():
+    """Eq. (3) and Eq. (5) at R = 4 against values evaluated by hand
+    (tests/golden/cache_block_r4.json): pins the R-dependent terms that the
+    R = 1 worked example cannot reach."""
+    import json
+    import os
+    from oracle import models
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cache_block_r4.json")) as f:
+        g = json.load(f)
+    for c in g["cases"]:
+        assert models.wavefront_width(c["Dw"], c["N_F"], c["R"]) == c["W_w"]
+        assert models.cache_block(c["Dw"], c["N_F"], 1.0, c["R"], c["N_D"]) == c["C_S_per_Nxb"]
+        assert models.cache_block(c["Dw"], c["N_F"], 128.0, c["R"], c["N_D"]) == 128 * c["C_S_per_Nxb"]
+        assert models.code_balance(c["Dw"], c["N_D"], c["R"]) == c["B_C_f64"]
