@@ -111,9 +111,10 @@ typedef struct {
  * (STENCIL_KIND_MIXED with nx = ny = nz = 0 for batched plans).  p == NULL
  * asks for the autotuned schedule (Sec. II-A: parameters are auto-tuned);
  * tuning runs at the first stencil_run (synchronously, on a proxy grid of
- * the same x-y extent that it allocates and frees), predicting the whole run
- * for that call's T; the choice is kept for the plan's later runs.  Errors: EINVAL (bad kind/dtype/size/params), EUNSUPPORTED
- * (parameters no kernel implements), ENOMEM. */
+ * the same x-y extent, at most 32 GiB of arrays, that it allocates and
+ * frees), predicting the whole run for that call's T; the choice is kept
+ * for the plan's later runs.  Errors: EINVAL (bad kind/dtype/size/params),
+ * EUNSUPPORTED (parameters no kernel implements), ENOMEM. */
 int stencil_create(stencil_plan **out, int32_t kind, int32_t dtype,
                    int32_t nx, int32_t ny, int32_t nz, const stencil_params *p);
 
@@ -122,13 +123,21 @@ int stencil_create(stencil_plan **out, int32_t kind, int32_t dtype,
  * (four more grid-sized arrays: two buffer pairs) on first use and keep it
  * until destroy; the
  * scratch holds intermediate levels so that concurrently running x-tiles
- * never read a value another tile overwrites.  Errors: EINVAL (null
- * pointers, size or dtype mismatch with the plan, halo < R, T < 0, bad
- * strides, cur not 0/1, coefficient kind mismatch), ENOMEM, EDEVICE. */
+ * never read a value another tile overwrites.  The MWD tile kernel
+ * addresses a padded plane with 32-bit byte offsets, so MWD runs grids whose
+ * plane (sz elements) is below 4 GiB; for a larger plane an explicit MWD
+ * plan fails with EUNSUPPORTED and an autotuned plan runs the naive sweep.
+ * Runs of one plan on different streams must be ordered by the caller (they
+ * share the plan's scratch).  Errors: EINVAL (null pointers, size or dtype
+ * mismatch with the plan, halo < R, T < 0, bad strides, cur not 0/1,
+ * coefficient kind mismatch) and EUNSUPPORTED, both before any device
+ * work; ENOMEM, EDEVICE. */
 int stencil_run(stencil_plan *plan, stencil_grid *grid, const stencil_coeffs *coeffs,
                 int32_t T, void *stream);
 
-/* Release a plan: waits for its work, frees its scratch and graphs. */
+/* Release a plan: waits for the plan's own last run (an event recorded on
+ * that run's stream; work on other streams is not waited for), then frees
+ * its scratch and graphs. */
 int stencil_destroy(stencil_plan *plan);
 
 /* Advance n independent grids (1 <= n <= 65535; uneven sizes, any kind; one
@@ -152,15 +161,20 @@ int stencil_destroy(stencil_plan *plan);
  * on `stream`; on return every grids[i].cur is updated as by stencil_run.
  * The plan must have been created with STENCIL_KIND_MIXED or the grids'
  * common kind.  MWD_TUNE=naive or MWD_TUNE=mwd (environment) forces every
- * grid onto one of the two schedules (a kind without a batched tile shape
- * stays naive).  Errors: as stencil_run; EINVAL for n outside 1..65535. */
+ * grid onto one of the two schedules (a kind without a batched tile shape,
+ * or a grid whose plane is 4 GiB or more, stays naive);
+ * MWD_BATCH_GROUP_BYTES (environment, bytes) replaces the 96 MiB budget of
+ * one group of naive grids.  Errors: as stencil_run; EINVAL for n outside
+ * 1..65535. */
 int stencil_run_batched(stencil_plan *plan, stencil_grid *grids, const stencil_coeffs *coeffs,
                         int32_t n, int32_t T, void *stream);
 
 /* FP64 norms over the interior, accumulated in FP64 whatever the grid dtype.
  * which = 0: of u = buf[cur]; which = 1: of the residual buf[cur] - buf[cur^1]
  * (u_T - u_{T-1} after a run).  out[0] = sqrt(sum of squares), out[1] = max
- * |.|.  Synchronous: returns after the result is on the host. */
+ * |.|, NaN if any interior value is NaN.  Synchronous: returns after the
+ * result is on the host.  Calls from several threads are serialised inside
+ * the library (the per-block partials live in one buffer per device). */
 int stencil_norms(const stencil_grid *grid, int32_t which, double out[2], void *stream);
 
 /* FP64 norms of a.buf[a.cur] - b.buf[b.cur] over the interior (same nx, ny,

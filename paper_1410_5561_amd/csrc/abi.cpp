@@ -111,7 +111,41 @@ struct stencil_plan {
     int scratch_halo, scratch_dev;
     BatchState* batch;
     Prof* prof;
+    // completion of the plan's last run (event on its stream), for destroy
+    hipEvent_t done;
+    int done_dev;
 };
+
+// Record the completion of a run on its stream (not while the stream is
+// being captured into a graph: a captured run completes when the graph does).
+static void mark_done(stencil_plan* p, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    if (p->done && p->done_dev != dev) {
+        // a run on another device: wait for the earlier one before the event is replaced
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+        p->done = nullptr;
+    }
+    if (!p->done) {
+        if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) {
+            p->done = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+        p->done_dev = dev;
+    }
+    if (hipEventRecord(p->done, s) != hipSuccess) (void)hipGetLastError();
+}
 
 static void free_scratch(stencil_plan* p)
 {
@@ -239,7 +273,12 @@ int stencil_create(stencil_plan** out, int32_t kind, int32_t dtype, int32_t nx, 
 int stencil_destroy(stencil_plan* p)
 {
     if (!p) return fail(STENCIL_EINVAL, "plan is NULL");
-    (void)hipDeviceSynchronize();
+    // wait for this plan's own last run only (other streams keep running)
+    if (p->done) {
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+        p->done = nullptr;
+    }
     free_scratch(p);
     batch_free(p->batch);
     if (p->prof) {
@@ -275,8 +314,15 @@ int stencil_run(stencil_plan* p, stencil_grid* g, const stencil_coeffs* c, int32
         p->shape = tc.shape;
         p->chosen = true;
     }
+    // the MWD tile kernel addresses a padded plane with 32-bit byte offsets
+    const bool plane_ok = mwd_plane_ok(g->sz, g->dtype);
+    if (p->mode == STENCIL_MODE_MWD && !plane_ok) {
+        if (!p->autotune)
+            return fail(STENCIL_EUNSUPPORTED, "MWD needs a padded plane (sz elements) below 4 GiB");
+    }
+    const int mode = (p->mode == STENCIL_MODE_MWD && !plane_ok) ? STENCIL_MODE_NAIVE : p->mode;
     DevGrid d = to_dev(g);
-    if (p->mode == STENCIL_MODE_NAIVE) {
+    if (mode == STENCIL_MODE_NAIVE) {
         for (int t = 0; t < T; ++t) {
             if (p->prof) p->prof->begin(s);
             hipError_t e = naive_sweep(d, w, d.org[(d.cur + t) & 1], d.org[(d.cur + t + 1) & 1], s);
@@ -289,6 +335,7 @@ int stencil_run(stencil_plan* p, stencil_grid* g, const stencil_coeffs* c, int32
         hipError_t e = mwd_run(d, w, T, p->shape, p->scratch_org, s, p->prof);
         if (e != hipSuccess) return hip_fail(e, "MWD launch");
     }
+    mark_done(p, s);
     g->cur ^= (T & 1);
     return STENCIL_OK;
 }
@@ -382,7 +429,9 @@ int stencil_run_batched(stencil_plan* p, stencil_grid* grids, const stencil_coef
                         int32_t T, void* stream)
 {
     if (!p) return fail(STENCIL_EINVAL, "plan is NULL");
-    return batch_run(p->kind, p->dtype, &p->batch, grids, coeffs, n, T, static_cast<hipStream_t>(stream));
+    const int rc = batch_run(p->kind, p->dtype, &p->batch, grids, coeffs, n, T, static_cast<hipStream_t>(stream));
+    if (rc == STENCIL_OK) mark_done(p, static_cast<hipStream_t>(stream));
+    return rc;
 }
 
 }  // extern "C"

@@ -1,6 +1,7 @@
 // Host side of the batched form: tile table, per-grid shapes, scratch, the
 // captured hipGraph and its replay.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -57,6 +58,18 @@ constexpr int kBatchXcdRun = 4;
 // together within the 256 MiB last-level cache
 constexpr size_t kCacheGroupBytes = size_t(96) << 20;
 constexpr int kNaiveBranches = 2;
+
+// The group budget; MWD_BATCH_GROUP_BYTES (environment, bytes) overrides it,
+// for tests that need many groups from a few small grids.
+static size_t cache_group_bytes()
+{
+    const char* e = std::getenv("MWD_BATCH_GROUP_BYTES");
+    if (e && *e) {
+        const long long v = std::atoll(e);
+        if (v > 0) return (size_t)v;
+    }
+    return kCacheGroupBytes;
+}
 // workgroups per launch below which a group's z chunks are halved
 constexpr long long kNaiveMinBlocks = 2048;
 // runs of this many consecutive naive blocks (neighbours in x and y, whose
@@ -105,7 +118,8 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     std::vector<int> var(n);
     for (int i = 0; i < n; ++i) {
         const TuneChoice c = tune_batch_choose(hw[i].kind, dtype, grids[i].nx, grids[i].ny, grids[i].nz, T_steps);
-        if (c.mode == STENCIL_MODE_NAIVE) {
+        // the tile kernel addresses a plane with 32-bit byte offsets
+        if (c.mode == STENCIL_MODE_NAIVE || !mwd_plane_ok(grids[i].sz, dtype)) {
             var[i] = -1;
             continue;
         }
@@ -198,6 +212,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
         std::vector<int> nidx;
         for (int i = 0; i < n; ++i)
             if (var[i] < 0) nidx.push_back(i);
+        const size_t group_bytes = cache_group_bytes();
         size_t k = 0;
         while (k < nidx.size()) {
             size_t bytes = 0, k1 = k;
@@ -205,7 +220,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
                 const stencil_grid& gg = grids[nidx[k1]];
                 const size_t gb = (size_t)(2 + narr_of(hw[nidx[k1]].kind)) * (size_t)gg.sz *
                                   (size_t)(gg.nz + 2 * gg.halo) * es_of(dtype);
-                if (k1 > k && bytes + gb > kCacheGroupBytes) break;
+                if (k1 > k && bytes + gb > group_bytes) break;
                 bytes += gb;
                 ++k1;
             }
@@ -334,7 +349,7 @@ static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* h
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         // boundary band into the scratch pairs first (each entry checks its own extent)
-        const dim3 hgrid(hgx, hgy, n);
+        const dim3 hgrid(hgx, std::min(hgy, kMaxGridYZ), n);
         hipError_t el = sizeof(T) == 8 ? batch_halo_launch_f64(reinterpret_cast<const HaloFill<double>*>(d_halo), hgrid, cs)
                                        : batch_halo_launch_f32(reinterpret_cast<const HaloFill<float>*>(d_halo), hgrid, cs);
         // the naive grids: group by group, one launch per time step; the

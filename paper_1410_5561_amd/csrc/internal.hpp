@@ -15,6 +15,13 @@ inline int radius_of(int kind) { return (kind == K7C || kind == K7V) ? 1 : 4; }
 inline int narr_of(int kind) { return kind == K7V ? 7 : (kind == K25V ? 13 : 0); }
 inline int ndomain_of(int kind) { return kind == K7C ? 2 : kind == K7V ? 9 : kind == K25C ? 2 : 15; }
 
+// The MWD tile kernel addresses a lane's column within a padded plane with a
+// 32-bit byte offset: it runs grids whose plane (sz elements) is below 4 GiB.
+inline bool mwd_plane_ok(long long sz, int dtype)
+{
+    return sz >= 0 && sz * (dtype == 0 ? 8LL : 4LL) < (1LL << 32);
+}
+
 // A grid as the kernels see it: pointers to the interior origin (element
 // (0,0,0)) of each buffer; halo >= R cells exist on every side.
 struct DevGrid {

@@ -3,6 +3,8 @@
 // kernel instantiations compile in parallel.
 #pragma once
 
+#include <algorithm>
+
 #include "internal.hpp"
 #include "mwd_tile.hpp"
 
@@ -25,18 +27,21 @@ __global__ void __launch_bounds__(256)
 mwd_gather_kernel(MwdArgs<T> a)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int z = blockIdx.z;
-    if (x >= a.nx || y >= a.ny) return;
-    const long long off = (long long)z * a.sz + (long long)y * a.sy + x;
+    if (x >= a.nx) return;
+    // y and z stride over the launch's blocks (gridDim.y, gridDim.z <= 65535)
+    for (int z = blockIdx.z; z < a.nz; z += gridDim.z) {
+        for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < a.ny; y += gridDim.y * 4) {
+            const long long off = (long long)z * a.sz + (long long)y * a.sy + x;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int t = a.nsteps - k;
-        if (t < 1) continue;
-        const int p = pair_of_row(row_of<R, DW>(y, t));
-        if (p != 0) {
-            const int bi = (a.cur + t) & 1;
-            a.pair[0][bi][off] = a.pair[p][bi][off];
+            for (int k = 0; k < 2; ++k) {
+                const int t = a.nsteps - k;
+                if (t < 1) continue;
+                const int p = pair_of_row(row_of<R, DW>(y, t));
+                if (p != 0) {
+                    const int bi = (a.cur + t) & 1;
+                    a.pair[0][bi][off] = a.pair[p][bi][off];
+                }
+            }
         }
     }
 }
@@ -85,7 +90,7 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         hf.r = G::R;
         hf.sy = g.sy;
         hf.sz = g.sz;
-        dim3 hg((g.nx + 2 * G::R + 63) / 64, (g.ny + 2 * G::R + 3) / 4, 1);
+        dim3 hg((g.nx + 2 * G::R + 63) / 64, std::min((g.ny + 2 * G::R + 3) / 4, kMaxGridYZ), 1);
         if (prof) prof->begin(stream);
         hipLaunchKernelGGL((mwd_halo_fill_kernel<T>), hg, dim3(256), 0, stream, hf);
         if (prof) prof->end(stream, 1);
@@ -106,7 +111,7 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         if (e != hipSuccess) return e;
     }
     if (!whole) return hipSuccess;
-    dim3 gg((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    dim3 gg((g.nx + 63) / 64, std::min((g.ny + 3) / 4, kMaxGridYZ), std::min(g.nz, kMaxGridYZ));
     if (prof) prof->begin(stream);
     hipLaunchKernelGGL((mwd_gather_kernel<T, G::R, DW>), gg, dim3(256), 0, stream, a);
     if (prof) prof->end(stream, 1);

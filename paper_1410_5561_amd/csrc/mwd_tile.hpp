@@ -206,21 +206,27 @@ struct HaloFill {
     long long sy, sz;
 };
 
+// Lanes take x; rows y stride over the grid's y blocks (the launch may have
+// fewer y blocks than the rows need: gridDim.y is at most 65535).
 template <typename T>
 __device__ __forceinline__ void halo_fill_one(const HaloFill<T>& e)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63) - e.r;
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6) - e.r;
-    if (x >= e.nx + e.r || y >= e.ny + e.r) return;
-    const bool col_inside = x >= 0 && x < e.nx && y >= 0 && y < e.ny;
-    for (int z = -e.r; z < e.nz + e.r; ++z) {
-        if (col_inside && z == 0) z = e.nz;  // skip the interior of an interior column
-        const long long off = (long long)z * e.sz + (long long)y * e.sy + x;
-        const T v = e.src[off];
+    if (x >= e.nx + e.r) return;
+    for (int y = blockIdx.y * 4 + (threadIdx.x >> 6) - e.r; y < e.ny + e.r; y += gridDim.y * 4) {
+        const bool col_inside = x >= 0 && x < e.nx && y >= 0 && y < e.ny;
+        for (int z = -e.r; z < e.nz + e.r; ++z) {
+            if (col_inside && z == 0) z = e.nz;  // skip the interior of an interior column
+            const long long off = (long long)z * e.sz + (long long)y * e.sy + x;
+            const T v = e.src[off];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) e.dst[k][off] = v;
+            for (int k = 0; k < 4; ++k) e.dst[k][off] = v;
+        }
     }
 }
+
+// Largest y or z extent of a launch grid.
+constexpr int kMaxGridYZ = 65535;
 
 template <typename T>
 __global__ void __launch_bounds__(256) mwd_halo_fill_kernel(HaloFill<T> e)

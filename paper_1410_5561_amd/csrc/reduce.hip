@@ -1,7 +1,13 @@
 // FP64 norms over the interior of a grid (or of a difference of two grids),
 // accumulated in FP64 whatever the storage precision: two passes, per-block
 // partial sums and maxima, then one block combines them in a fixed order, so
-// a result is reproducible run to run.
+// a result is reproducible run to run.  The max propagates NaN: a NaN
+// anywhere in the interior makes the max norm NaN.
+//
+// The per-block partials live in a buffer the library allocates once per
+// device; a call is synchronous (result on the host) and holds a lock from
+// launch to completion, so concurrent calls from several threads do not
+// share it.
 #include <mutex>
 
 #include "common.hpp"
@@ -11,6 +17,14 @@ namespace mwd {
 
 constexpr int kNormThreads = 256;
 constexpr int kNormMaxBlocks = 2048;
+// partial sums and maxima of at most kNormMaxBlocks blocks
+constexpr int kNormPartials = 2 * kNormMaxBlocks;
+
+// max(m, |v|) that keeps a NaN once one is seen (fmax would drop it)
+__device__ __forceinline__ double nan_max(double m, double v)
+{
+    return (v > m || v != v) ? v : m;
+}
 
 template <typename TA, typename TB, bool DIFF>
 __global__ void __launch_bounds__(kNormThreads)
@@ -31,7 +45,7 @@ norm_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, int nx, 
             double v = (double)ar[x];
             if (DIFF) v = v - (double)br[x];
             s += v * v;
-            m = fmax(m, fabs(v));
+            m = nan_max(m, fabs(v));
         }
     }
     ssum[threadIdx.x] = s;
@@ -40,7 +54,7 @@ norm_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, int nx, 
     for (int w = kNormThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
             ssum[threadIdx.x] += ssum[threadIdx.x + w];
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            smax[threadIdx.x] = nan_max(smax[threadIdx.x], smax[threadIdx.x + w]);
         }
         __syncthreads();
     }
@@ -58,7 +72,7 @@ norm_final_kernel(const double* __restrict__ part, int nblocks, double* __restri
     double s = 0.0, m = 0.0;
     for (int i = threadIdx.x; i < nblocks; i += kNormThreads) {
         s += part[2 * i];
-        m = fmax(m, part[2 * i + 1]);
+        m = nan_max(m, part[2 * i + 1]);
     }
     ssum[threadIdx.x] = s;
     smax[threadIdx.x] = m;
@@ -66,7 +80,7 @@ norm_final_kernel(const double* __restrict__ part, int nblocks, double* __restri
     for (int w = kNormThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
             ssum[threadIdx.x] += ssum[threadIdx.x + w];
-            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+            smax[threadIdx.x] = nan_max(smax[threadIdx.x], smax[threadIdx.x + w]);
         }
         __syncthreads();
     }
@@ -76,20 +90,20 @@ norm_final_kernel(const double* __restrict__ part, int nblocks, double* __restri
     }
 }
 
-// Device scratch for the partials, one per device, kept for the process.
-static std::mutex g_norm_mu;
-static double* g_norm_buf[64] = {nullptr};
+constexpr int kMaxDevices = 64;
 
-static hipError_t norm_buffer(double** out)
+// The buffer of norms_fp64, one per device, kept for the process.
+static std::mutex g_norm_mu;
+static double* g_norm_buf[kMaxDevices] = {nullptr};
+
+static hipError_t norm_buffer(int dev, double** out)
 {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    std::lock_guard<std::mutex> lk(g_norm_mu);
     if (!g_norm_buf[dev]) {
-        e = hipMalloc(&g_norm_buf[dev], sizeof(double) * (2 * kNormMaxBlocks + 2));
-        if (e != hipSuccess) return e;
+        hipError_t e = hipMalloc(&g_norm_buf[dev], sizeof(double) * (kNormPartials + 2));
+        if (e != hipSuccess) {
+            g_norm_buf[dev] = nullptr;
+            return e;
+        }
     }
     *out = g_norm_buf[dev];
     return hipSuccess;
@@ -109,27 +123,42 @@ static void launch_norm(const DevGrid& ga, const void* a, const DevGrid& gb, con
                            ga.nz, ga.sy, ga.sz, gb.sy, gb.sz, part);
 }
 
-hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b, int which,
-                      double out[2], hipStream_t stream)
+// Both passes on `stream`: partials into part[0 .. 2 nblocks), the two
+// results into out (device memory).  Every partial slot the final pass reads
+// is written by this call's first pass, so nothing needs clearing.
+static hipError_t norm_passes(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b, int which,
+                              double* part, double* out, hipStream_t stream)
 {
-    double* buf = nullptr;
-    hipError_t e = norm_buffer(&buf);
-    if (e != hipSuccess) return e;
     const long long rows = (long long)ga.ny * ga.nz;
     const int nblocks = (int)(rows < kNormMaxBlocks ? rows : kNormMaxBlocks);
     const bool diff = which != 0;
     const bool fa = ga.dtype == 0, fb = gb.dtype == 0;
-    if (fa && fb) launch_norm<double, double>(ga, a, gb, b, diff, nblocks, buf, stream);
-    else if (fa && !fb) launch_norm<double, float>(ga, a, gb, b, diff, nblocks, buf, stream);
-    else if (!fa && fb) launch_norm<float, double>(ga, a, gb, b, diff, nblocks, buf, stream);
-    else launch_norm<float, float>(ga, a, gb, b, diff, nblocks, buf, stream);
-    e = hipGetLastError();
+    if (fa && fb) launch_norm<double, double>(ga, a, gb, b, diff, nblocks, part, stream);
+    else if (fa && !fb) launch_norm<double, float>(ga, a, gb, b, diff, nblocks, part, stream);
+    else if (!fa && fb) launch_norm<float, double>(ga, a, gb, b, diff, nblocks, part, stream);
+    else launch_norm<float, float>(ga, a, gb, b, diff, nblocks, part, stream);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormThreads), 0, stream, buf, nblocks,
-                       buf + 2 * kNormMaxBlocks);
-    e = hipGetLastError();
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormThreads), 0, stream, part, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b, int which,
+                      double out[2], hipStream_t stream)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(out, buf + 2 * kNormMaxBlocks, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    // one buffer per device: held from the first launch until the result is
+    // on the host
+    std::lock_guard<std::mutex> lk(g_norm_mu);
+    double* buf = nullptr;
+    e = norm_buffer(dev, &buf);
+    if (e != hipSuccess) return e;
+    e = norm_passes(ga, a, gb, b, which, buf, buf + kNormPartials, stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(out, buf + kNormPartials, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(stream);
 }

@@ -128,3 +128,32 @@ def test_norm_argument_checks(L):
     assert L.stencil_norms(ctypes.byref(_grid()), 2, out, None) == EINVAL
     assert L.stencil_norms(ctypes.byref(_grid()), 0, None, None) == EINVAL
     assert L.stencil_diff_norms(ctypes.byref(_grid()), ctypes.byref(_grid(nx=7)), out, None) == EINVAL
+
+
+def test_mwd_rejects_planes_of_4gib_before_any_device_work(L):
+    """The tile kernel addresses a padded plane with 32-bit byte offsets: an
+    explicit MWD plan refuses a grid whose plane is 4 GiB or more (fake
+    device pointers: the call must not touch them)."""
+    rc, p = _rc_create(L, 0, 0, 8, 8, 8, S.StencilParams(2, 8, 64, 0))
+    assert rc == 0
+    c = S.make_coeffs("7c", consts=[0.4, 0.1])
+    g = _grid()
+    g.sz = (1 << 29)                    # 2^29 doubles = 4 GiB per plane
+    assert L.stencil_run(p, ctypes.byref(g), ctypes.byref(c), 3, None) == EUNSUPPORTED
+    assert "4 GiB" in S.stencil_last_error()
+    g.sz = (1 << 29) - 8                # just below: accepted by the check (not run here)
+    assert g.sz * 8 < (1 << 32)
+    L.stencil_destroy(p)
+    # FP32: the limit is 2^30 elements
+    rc, p = _rc_create(L, 0, 1, 8, 8, 8, S.StencilParams(2, 8, 64, 0))
+    assert rc == 0
+    g = _grid(dtype=1)
+    g.sz = 1 << 30
+    assert L.stencil_run(p, ctypes.byref(g), ctypes.byref(c), 3, None) == EUNSUPPORTED
+    L.stencil_destroy(p)
+
+
+def test_destroy_without_runs_needs_no_device(L):
+    rc, p = _rc_create(L, 2, 1, 16, 16, 16, S.StencilParams(2, 16, 64, 0))
+    assert rc == 0
+    assert L.stencil_destroy(p) == 0

@@ -92,3 +92,83 @@ def test_norms_against_oracle(dts):
     rd = onorms.diff_norms(uT, u64, 1, 1)
     assert abs(d2[0] - rd[0]) <= 1e-13 * rd[0] and d2[1] == rd[1]
     plan.close()
+
+
+@pytest.mark.parametrize("dts", ["f32", "f64"])
+def test_batched_many_naive_groups(dts, monkeypatch):
+    """Groups small enough that every naive grid forms its own group: the
+    graph alternates groups between its two concurrent branches and joins
+    them; every grid matches the oracle after two replays."""
+    import torch
+    monkeypatch.setenv("MWD_TUNE", "naive")
+    monkeypatch.setenv("MWD_BATCH_GROUP_BYTES", "200000")
+    dtype = np.float64 if dts == "f64" else np.float32
+    T = 7
+    print("batched many groups", dts, flush=True)
+    inputs = [_inputs(k, n, dtype, 300 + i) for i, (k, n) in enumerate(SPECS)]
+    grids, keep, coeffs = [], [], []
+    for (kind, n), (u0, co) in zip(SPECS, inputs):
+        g, bufs = device_grid(u0, gridgen.RADIUS[kind], 0)
+        c, ck = device_coeffs(kind, co, dtype)
+        grids.append(g)
+        keep.append((bufs, ck))
+        coeffs.append(c)
+    plan = S.Plan("mixed", dts)
+    for rep in (1, 2):
+        plan.run_batched(grids, coeffs, T)
+        torch.cuda.synchronize()
+        for i, ((kind, n), (u0, co)) in enumerate(zip(SPECS, inputs)):
+            bufs = keep[i][0]
+            uT, uTm1 = oracle.run(kind, u0, co, rep * T)
+            assert np.array_equal(bufs[grids[i].cur].cpu().numpy(), uT), "grid %d after %d runs" % (i, rep)
+            assert np.array_equal(bufs[grids[i].cur ^ 1].cpu().numpy(), uTm1), "grid %d u_{T-1}" % i
+    plan.close()
+
+
+def test_batched_workload5_every_grid_against_oracle():
+    """The batching workload as configured (256 grids, sides 32..256, half
+    7-point and half 25-point constant, FP32, T = 16), with the schedule the
+    tuner picks per grid: every grid bit-exact against the oracle."""
+    import torch
+    w = gridgen.workloads()[5]
+    T = w["T"]
+    specs = gridgen.batch_specs(count=w["count"])
+    print("workload 5: generating", len(specs), "grids", flush=True)
+    grids, keep, coeffs, fields = [], [], [], []
+    for sp in specs:
+        u0 = gridgen.batch_field(sp, np.float32)
+        fields.append(u0)
+        d = torch.from_numpy(u0).cuda()
+        keep.append((d, d.clone()))
+        grids.append(S.make_grid(keep[-1][0], keep[-1][1], sp["halo"], 0))
+        coeffs.append(S.make_coeffs(sp["kind"], consts=sp["coeffs"]))
+    plan = S.Plan("mixed", "f32")
+    print("workload 5: running", flush=True)
+    plan.run_batched(grids, coeffs, T)
+    torch.cuda.synchronize()
+    for i, sp in enumerate(specs):
+        uT, uTm1 = oracle.run(sp["kind"], fields[i], sp["coeffs"], T)
+        got = keep[i][grids[i].cur].cpu().numpy()
+        assert np.array_equal(got, uT), "grid %d (%s %s)" % (i, sp["kind"], sp["n"])
+        assert np.array_equal(keep[i][grids[i].cur ^ 1].cpu().numpy(), uTm1), "grid %d u_{T-1}" % i
+        if i % 32 == 31:
+            print("workload 5: %d grids checked" % (i + 1), flush=True)
+    plan.close()
+
+
+@pytest.mark.parametrize("dts", ["f64", "f32"])
+def test_norms_propagate_nan(dts):
+    """One NaN in the interior makes both norms NaN; NaN in the halo does not
+    enter."""
+    dtype = np.float64 if dts == "f64" else np.float32
+    n = (33, 20, 9)
+    u0 = gridgen.field(12, *n, 1, 0.0, 1.0, dtype)
+    u0[0, 0, 0] = np.nan                       # a halo corner
+    g, bufs = device_grid(u0, 1, 0)
+    l2, mx = S.stencil_norms(g, 0)
+    rl2, rmx = onorms.grid_norms(u0, 1)
+    assert np.isfinite(l2) and mx == rmx and abs(l2 - rl2) <= 1e-13 * rl2
+    u0[5, 7, 11] = np.nan
+    g, bufs = device_grid(u0, 1, 0)
+    l2, mx = S.stencil_norms(g, 0)
+    assert np.isnan(l2) and np.isnan(mx)

@@ -58,6 +58,15 @@ def _check_samples(w, u0, co, g, bufs, count):
         got = res[p[2] + R, p[1] + R, p[0] + R].item()
         ref = cone.subbox_value(kind, u0, co, T, R, p)
         assert got == ref, "point %s: gpu %r oracle %r" % (p, got, ref)
+    # whole x rows and y columns: every x tile seam and every diamond they cross
+    checked = count
+    for lo, hi in cone.line_boxes(n, T, R, seed=T):
+        got = res[lo[2] + R:hi[2] + R, lo[1] + R:hi[1] + R, lo[0] + R:hi[0] + R].cpu().numpy()
+        ref = cone.box_values(kind, u0, co, T, R, lo, hi)
+        bad = np.argwhere(got != ref)
+        assert bad.size == 0, "box %s-%s: %d points differ, first at %s" % (lo, hi, len(bad), bad[0])
+        checked += got.size
+    print("workload %s: %d sampled points bit-exact" % (w["name"], checked), flush=True)
 
 
 @pytest.mark.parametrize("windex,dtype,count", [(2, "f64", 10), (3, "f64", 5), (3, "f32", 5),

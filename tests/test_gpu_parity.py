@@ -52,15 +52,16 @@ def test_naive_bitexact(kind, dtype):
     _check(kind, u0, co, 5, *got)
 
 
+# every compiled (diamond width, x lanes) shape
 MWD_SHAPES = {
-    ("7c", "f64"): [(4, 64), (4, 128), (8, 64), (8, 128)],
-    ("7c", "f32"): [(4, 64), (4, 128), (8, 64), (8, 128), (16, 64)],
-    ("7v", "f64"): [(4, 64), (4, 128), (8, 64), (8, 128)],
-    ("7v", "f32"): [(4, 64), (4, 128), (8, 64), (8, 128), (16, 64)],
-    ("25c", "f64"): [(8, 64), (16, 64)],
-    ("25c", "f32"): [(8, 64), (16, 64)],
-    ("25v", "f64"): [(8, 64), (16, 64)],
-    ("25v", "f32"): [(8, 64), (16, 64)],
+    ("7c", "f64"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128)],
+    ("7c", "f32"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
+    ("7v", "f64"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128)],
+    ("7v", "f32"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
+    ("25c", "f64"): [(8, 64), (8, 128), (16, 64)],
+    ("25c", "f32"): [(8, 64), (8, 128), (16, 64)],
+    ("25v", "f64"): [(8, 64), (8, 128), (16, 64)],
+    ("25v", "f32"): [(8, 64), (8, 128), (16, 64)],
 }
 MWD_CASES = [(k, d, dw, lx) for (k, d), shapes in MWD_SHAPES.items() for (dw, lx) in shapes]
 
@@ -72,6 +73,8 @@ def test_mwd_bitexact(case):
     # several x tiles with a ragged last one, several diamonds per row with
     # half diamonds at both y edges, many rows
     n = (150, 45, 19) if kind in ("7c", "7v") else (140, 53, 17)
+    if lanes == 256:
+        n = (530, 45, 19)   # several 256-lane x tiles and a ragged one
     T = 13 if kind in ("7c", "7v") else 7
     print("mwd", case, n, T, flush=True)
     u0, co = _inputs(kind, n, dtype)
@@ -88,6 +91,8 @@ def test_mwd_bitexact_steady_state(case):
     kind, dts, dw, lanes = case
     dtype = np.float64 if dts == "f64" else np.float32
     n = (160, 40, 70) if kind in ("7c", "7v") else (150, 60, 70)
+    if lanes == 256:
+        n = (600, 40, 70)
     T = 6
     print("mwd steady", case, n, T, flush=True)
     u0, co = _inputs(kind, n, dtype, seed=23)
@@ -170,3 +175,20 @@ def test_f32_against_f64_oracle_bound():
     ref, _ = oracle.run("7v", u0.astype(np.float64), [c.astype(np.float64) for c in C], T)
     err = np.max(np.abs(got.astype(np.float64) - ref))
     assert err <= T * 14 * 2.0 ** -24 * float(np.max(u0))
+
+
+@pytest.mark.parametrize("case", [("7c", (1, 2, 70000), 5), ("25c", (3, 1, 66000), 3),
+                                  ("7c", (2, 270000, 2), 4)],
+                         ids=["7c-nz70000", "25c-nz66000", "7c-ny270000"])
+def test_extents_beyond_the_launch_grid_limit(case):
+    """z or y extents above 65535 (the y/z limit of a launch grid): the MWD
+    gather and boundary fill stride over their launch, the naive sweep uses a
+    one-dimensional grid."""
+    kind, n, T = case
+    print("large extent", kind, n, T, flush=True)
+    u0, co = _inputs(kind, n, np.float64, seed=41)
+    dw = 8 if kind == "7c" else 16
+    got = run_gpu(kind, u0, co, T, mode="mwd", dw=dw, lanes=64)
+    _check(kind, u0, co, T, *got)
+    got = run_gpu(kind, u0, co, T, mode="naive")
+    _check(kind, u0, co, T, *got)
