@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--cpu-T", type=int, default=0, help="time steps of the oracle sample")
     ap.add_argument("--sweep", action="store_true",
                     help="also time every compiled MWD shape (diamond width x lanes)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other workloads (4 in FP32, 3 in FP64 and FP32, 5) that the "
+                         "default line reports beside the headline workload")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each other workload")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -240,9 +244,10 @@ def cpu_baseline(w, dtype, windex, T_cpu, min_s=10.0, max_reps=20):
                 w["kind"] + "-" + dtype, nx, ny, nz, steps, steps // T_cpu, T_cpu, dt)}
 
 
-def bench_batch(a, torch, S):
+def batch_measure(a, torch, S, steps, warmup):
     """Workload 5: many uneven grids (7-point and 25-point constant, FP32)
-    advanced together with one hipGraph launch per step."""
+    advanced together with one hipGraph launch per step.  Returns
+    (GLUP/s, seconds of the timed steps, grids, LUPs per step)."""
     import gridgen
     w = gridgen.workloads()[5]
     T = w["T"]
@@ -259,17 +264,27 @@ def bench_batch(a, torch, S):
         nx, ny, nz = sp["n"]
         lups += nx * ny * nz * T
     plan = S.Plan("mixed", "f32")
-    for _ in range(a.warmup):
+    for _ in range(max(1, warmup)):
         plan.run_batched(grids, coeffs, T)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(a.steps):
+    for _ in range(steps):
         plan.run_batched(grids, coeffs, T)
     e1.record()
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3
-    value = a.steps * lups / sec / 1e9
+    plan.close()
+    del keep
+    return steps * lups / sec / 1e9, sec, len(specs), lups
+
+
+def bench_batch(a, torch, S):
+    """The batching workload as the headline line (--workload 5)."""
+    import gridgen
+    w = gridgen.workloads()[5]
+    T = w["T"]
+    value, sec, ngrids, lups = batch_measure(a, torch, S, a.steps, a.warmup)
     # model bytes: each grid at its own Eq. (5) balance would need the tuned
     # shapes; report the naive-sweep balance (s N_D = 8 B/LUP) as the ceiling
     out = {
@@ -278,11 +293,56 @@ def bench_batch(a, torch, S):
         "warmup": a.warmup, "ms_per_step": round(sec * 1e3 / a.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w["name"], "grids": len(specs), "T": T, "lups_per_step": lups},
+        "config": {"workload": w["name"], "grids": ngrids, "T": T, "lups_per_step": lups},
     }
-    plan.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def other_workload(a, torch, S, windex, dtype):
+    """A compact line for one more workload: the autotuned plan against the
+    naive sweep, both timed over whole runs with inputs resident."""
+    import gridgen
+    w = gridgen.workloads()[windex]
+    kind, (nx, ny, nz), T = w["kind"], w["n"], w["T"]
+    R = gridgen.RADIUS[kind]
+    lups = nx * ny * nz * T
+    log(a, "other workload", w["name"], dtype)
+    u0, co = make_inputs(w, dtype, windex)
+    u0_dev = torch.from_numpy(u0).cuda()
+    co_dev = co if kind in ("7c", "25c") else [torch.from_numpy(c).cuda() for c in co]
+    del u0, co
+    steps = a.extra_steps
+    sec, _, desc, prof, state = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev, co_dev, T,
+                                          steps, 1, "auto", 0, 0, R)
+    del state
+    value = steps * lups / sec / 1e9
+    mode_name = {0: "auto", 1: "naive", 2: "mwd"}[desc["mode"]]
+    bpl = desc["model_bytes_per_lup"]
+    launches = max(1, prof["main_launches"])
+    achieved = bpl * lups * steps / launches / (prof["main_ms"] / 1e3 / launches) / 1e9
+    res = {"workload": w["name"], "dtype": dtype, "value": round(value, 3), "unit": "GLUP/s",
+           "steps": steps, "ms_per_step": round(sec * 1e3 / steps, 3),
+           "schedule": {"mode": mode_name, "dw": desc["dw"], "lanes": desc["lanes"]},
+           "model_bytes_per_lup": round(bpl, 4),
+           "roofline": {"bound": "hbm", "kernel": "mwd_row_kernel" if mode_name == "mwd" else "naive_sweep_kernel",
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "avg_launch_us": round(prof["main_ms"] * 1e3 / launches, 2)},
+           "norms_fp64": desc["norms"]}
+    if mode_name != "naive":
+        nsec, _, ndesc, _, nstate = time_mode(S, torch, kind, dtype, (nx, ny, nz), u0_dev, co_dev, T,
+                                              max(1, a.naive_steps), 1, "naive", 0, 0, R)
+        del nstate
+        nval = max(1, a.naive_steps) * lups / nsec / 1e9
+        res["naive"] = {"value": round(nval, 3), "ms_per_step": round(nsec * 1e3 / max(1, a.naive_steps), 3),
+                        "model_bytes_per_lup": ndesc["model_bytes_per_lup"]}
+        res["speedup_vs_naive"] = round(value / nval, 3)
+    del u0_dev, co_dev
+    torch.cuda.empty_cache()
+    if dtype == "f32" and not a.no_precision and "error_subrun" in w:
+        res["fp32_vs_fp64"] = precision_subrun(S, torch, w, windex, n=tuple(w["error_subrun"]))
+    return res
 
 
 def main():
@@ -413,6 +473,22 @@ def main():
         log(a, "precision sub-run")
         out["fp32_vs_fp64"] = precision_subrun(S, torch, w, a.workload,
                                                 n=tuple(w.get("error_subrun", (256, 256, 256))))
+    if not a.no_extra and a.workload == 2:
+        # the other single-grid workloads (the FP32 precision form, the
+        # radius-4 star in both precisions) and the batching workload
+        del state
+        state = None
+        del u0_dev, co_dev
+        torch.cuda.empty_cache()
+        extra = []
+        for windex, edt in ((4, "f32"), (3, "f64"), (3, "f32")):
+            extra.append(other_workload(a, torch, S, windex, edt))
+        bval, bsec, bn, blups = batch_measure(a, torch, S, a.extra_steps, 1)
+        extra.append({"workload": gridgen.workloads()[5]["name"], "dtype": "f32", "value": round(bval, 3),
+                      "unit": "GLUP/s", "steps": a.extra_steps,
+                      "ms_per_step": round(bsec * 1e3 / a.extra_steps, 3), "grids": bn})
+        out["other_workloads"] = extra
+        torch.cuda.empty_cache()
     # practical bandwidth reference: streaming copy of 2 GiB
     nbytes = 1 << 31
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -432,7 +508,7 @@ def main():
     if not a.no_cpu_baseline:
         log(a, "cpu baseline")
         Tc = a.cpu_T or T
-        del state
+        state = None
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(w, dtype, a.workload, Tc)
     print(json.dumps(out), flush=True)

@@ -13,6 +13,7 @@ import argparse
 import concurrent.futures as cf
 import glob
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -36,9 +37,25 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _headers_mtime():
-    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
-    return max((os.path.getmtime(h) for h in hs), default=0.0)
+_INCLUDE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _deps(src, seen=None):
+    """The file and every local header it includes, transitively."""
+    seen = set() if seen is None else seen
+    src = os.path.normpath(src)
+    if src in seen or not os.path.exists(src):
+        return seen
+    seen.add(src)
+    with open(src) as f:
+        text = f.read()
+    for inc in _INCLUDE.findall(text):
+        _deps(os.path.join(os.path.dirname(src), inc), seen)
+    return seen
+
+
+def _deps_mtime(src):
+    return max(os.path.getmtime(d) for d in _deps(src))
 
 
 def _obj(src):
@@ -62,11 +79,10 @@ def _compile(src, resource_usage):
 def build(force: bool = False, jobs: int | None = None, resource_usage: bool = False,
           verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    hdr = _headers_mtime()
     todo = []
     for s in sources():
         o = _obj(s)
-        if force or not os.path.exists(o) or os.path.getmtime(o) < max(os.path.getmtime(s), hdr):
+        if force or not os.path.exists(o) or os.path.getmtime(o) < _deps_mtime(s):
             todo.append(s)
     jobs = jobs or min(8, os.cpu_count() or 4)
     logs = {}
