@@ -182,6 +182,20 @@ int stencil_norms(const stencil_grid *grid, int32_t which, double out[2], void *
  * Synchronous. */
 int stencil_diff_norms(const stencil_grid *a, const stencil_grid *b, double out[2], void *stream);
 
+/* The norms of stencil_norms without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The per-block partials
+ * live in a fixed 32 KiB array inside the loaded library (one per device,
+ * kept until the process ends; every grid size fits, since the reduction
+ * uses at most 2048 blocks); the call allocates nothing and synchronises
+ * nothing.  out_dev: caller-owned device memory for two doubles (8-byte
+ * aligned), written asynchronously on `stream`: out_dev[0] = L2 norm,
+ * out_dev[1] = max norm, of u (which = 0) or of the residual (which = 1),
+ * bit-identical to stencil_norms on the same grid.  Calls that overlap on
+ * one device share the array and race: order them (one stream, or events).
+ * Errors: EINVAL (as stencil_norms, or out_dev NULL or misaligned), EDEVICE. */
+int stencil_norms_noalloc(const stencil_grid *grid, int32_t which, double *out_dev, void *stream);
+
 /* Describe a plan's chosen schedule (after the first run for autotuned plans). */
 int stencil_plan_describe(const stencil_plan *plan, stencil_plan_desc *out);
 

@@ -14,7 +14,7 @@ import os
 __all__ = [
     "KIND", "DTYPE", "MODE", "StencilError", "lib", "lib_path",
     "stencil_create", "stencil_run", "stencil_destroy", "stencil_run_batched",
-    "stencil_norms", "stencil_diff_norms", "stencil_plan_describe",
+    "stencil_norms", "stencil_norms_noalloc", "stencil_diff_norms", "stencil_plan_describe",
     "stencil_model_bytes_per_lup", "stencil_strerror", "stencil_last_error",
     "stencil_abi_version", "stencil_profile_enable", "stencil_profile_read",
     "stencil_stream_copy", "Plan", "make_grid", "make_coeffs", "padded_empty", "radius",
@@ -79,6 +79,8 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "stencil_diff_norms": (ctypes.c_int, [ctypes.POINTER(StencilGrid), ctypes.POINTER(StencilGrid),
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "stencil_norms_noalloc": (ctypes.c_int, [ctypes.POINTER(StencilGrid), ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "stencil_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StencilPlanDesc)]),
     "stencil_model_bytes_per_lup": (ctypes.c_double, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "stencil_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -182,6 +184,12 @@ def stencil_norms(grid: StencilGrid, which: int = 0, stream=None) -> tuple[float
     _check(lib().stencil_norms(ctypes.byref(grid), int(which), out, _stream_ptr(stream)),
            "stencil_norms")
     return out[0], out[1]
+
+
+def stencil_norms_noalloc(grid: StencilGrid, which: int, out_dev_ptr: int, stream=None):
+    """Asynchronous, allocation-free norms into two doubles of device memory."""
+    _check(lib().stencil_norms_noalloc(ctypes.byref(grid), int(which), ctypes.c_void_p(out_dev_ptr),
+                                       _stream_ptr(stream)), "stencil_norms_noalloc")
 
 
 def stencil_diff_norms(a: StencilGrid, b: StencilGrid, stream=None) -> tuple[float, float]:

@@ -10,6 +10,7 @@
 #include "../../include/mwd_stencil.h"
 #include "batch.hpp"
 #include "internal.hpp"
+#include "reduce.hpp"
 #include "tune.hpp"
 
 namespace mwd {
@@ -432,6 +433,21 @@ int stencil_run_batched(stencil_plan* p, stencil_grid* grids, const stencil_coef
     const int rc = batch_run(p->kind, p->dtype, &p->batch, grids, coeffs, n, T, static_cast<hipStream_t>(stream));
     if (rc == STENCIL_OK) mark_done(p, static_cast<hipStream_t>(stream));
     return rc;
+}
+
+int stencil_norms_noalloc(const stencil_grid* g, int32_t which, double* out_dev, void* stream)
+{
+    int rc = check_grid(g, "grid");
+    if (rc) return rc;
+    if (!out_dev) return fail(STENCIL_EINVAL, "out_dev is NULL");
+    if (reinterpret_cast<uintptr_t>(out_dev) % sizeof(double))
+        return fail(STENCIL_EINVAL, "out_dev is not 8-byte aligned");
+    if (which != 0 && which != 1) return fail(STENCIL_EINVAL, "which must be 0 or 1");
+    DevGrid d = to_dev(g);
+    hipError_t e = norms_fp64_static(d, d.org[d.cur], d, d.org[d.cur ^ 1], which, out_dev,
+                                     static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "norms (static scratch)");
+    return STENCIL_OK;
 }
 
 }  // extern "C"

@@ -4,14 +4,19 @@
 // a result is reproducible run to run.  The max propagates NaN: a NaN
 // anywhere in the interior makes the max norm NaN.
 //
-// The per-block partials live in a buffer the library allocates once per
-// device; a call is synchronous (result on the host) and holds a lock from
-// launch to completion, so concurrent calls from several threads do not
-// share it.
+// Two ways to hold the per-block partials:
+//   - norms_fp64: a buffer the library allocates once per device; the call
+//     is synchronous (result on the host) and holds a lock from launch to
+//     completion, so concurrent calls from several threads do not share it;
+//   - norms_fp64_static: a fixed array in the library's device memory
+//     (`scratch` below), so the call allocates nothing; the result goes to
+//     caller-owned device memory, asynchronously.  Calls that overlap on one
+//     device share that array and race.
 #include <mutex>
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "reduce.hpp"
 
 namespace mwd {
 
@@ -90,11 +95,22 @@ norm_final_kernel(const double* __restrict__ part, int nblocks, double* __restri
     }
 }
 
+// Partials of the allocation-free entry point: one copy per device, held by
+// the loaded library until the process ends (32 KiB).  Host code never uses
+// this name as an address: it takes the device address once per device with
+// hipGetSymbolAddress and passes that.
+static __device__ __align__(256) double scratch[kNormPartials];
+
 constexpr int kMaxDevices = 64;
 
 // The buffer of norms_fp64, one per device, kept for the process.
 static std::mutex g_norm_mu;
 static double* g_norm_buf[kMaxDevices] = {nullptr};
+
+// Device address of `scratch`, one per device, taken at the first use on
+// that device with the device current.
+static std::mutex g_static_mu;
+static double* g_static_ptr[kMaxDevices] = {nullptr};
 
 static hipError_t norm_buffer(int dev, double** out)
 {
@@ -106,6 +122,24 @@ static hipError_t norm_buffer(int dev, double** out)
         }
     }
     *out = g_norm_buf[dev];
+    return hipSuccess;
+}
+
+static hipError_t static_scratch(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_static_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_static_ptr[dev];
     return hipSuccess;
 }
 
@@ -161,6 +195,15 @@ hipError_t norms_fp64(const DevGrid& ga, const void* a, const DevGrid& gb, const
     e = hipMemcpyAsync(out, buf + kNormPartials, 2 * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(stream);
+}
+
+hipError_t norms_fp64_static(const DevGrid& ga, const void* a, const DevGrid& gb, const void* b, int which,
+                             double* out_dev, hipStream_t stream)
+{
+    double* part = nullptr;
+    hipError_t e = static_scratch(&part);
+    if (e != hipSuccess) return e;
+    return norm_passes(ga, a, gb, b, which, part, out_dev, stream);
 }
 
 }  // namespace mwd
