@@ -43,25 +43,25 @@ __device__ __forceinline__ void batch_naive_tile(const NaiveLaunch<T>& L, char* 
     T* dst = a.buf[(a.cur + L.t + 1) & 1];
     switch (a.kind) {
         case K7C:
-            naive_block<K7C, T, kNaiveBX, kNaiveBY>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
-                                                    e.by, e.bz, reinterpret_cast<T (*)[kNaiveBX + 2]>(lds));
+            naive_block<K7C, T, kNaiveBX, kNaiveBY, naive_prefetch<K7C, T>(true), true>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
+                                                    e.by, e.bz, reinterpret_cast<T (*)[kNaiveBY + 2][kNaiveBX + 2]>(lds));
             break;
         case K7V:
-            naive_block<K7V, T, kNaiveBX, kNaiveBY>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
-                                                    e.by, e.bz, reinterpret_cast<T (*)[kNaiveBX + 2]>(lds));
+            naive_block<K7V, T, kNaiveBX, kNaiveBY, naive_prefetch<K7V, T>(true), true>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
+                                                    e.by, e.bz, reinterpret_cast<T (*)[kNaiveBY + 2][kNaiveBX + 2]>(lds));
             break;
         case K25C:
-            naive_block<K25C, T, kNaiveBX, kNaiveBY>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
-                                                     e.by, e.bz, reinterpret_cast<T (*)[kNaiveBX + 8]>(lds));
+            naive_block<K25C, T, kNaiveBX, kNaiveBY, naive_prefetch<K25C, T>(true), true>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
+                                                     e.by, e.bz, reinterpret_cast<T (*)[kNaiveBY + 8][kNaiveBX + 8]>(lds));
             break;
         default:
-            naive_block<K25V, T, kNaiveBX, kNaiveBY>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
-                                                     e.by, e.bz, reinterpret_cast<T (*)[kNaiveBX + 8]>(lds));
+            naive_block<K25V, T, kNaiveBX, kNaiveBY, naive_prefetch<K25V, T>(true), true>(src, dst, a.w, a.nx, a.ny, a.nz, a.sy, a.sz, a.zchunk, e.bx,
+                                                     e.by, e.bz, reinterpret_cast<T (*)[kNaiveBY + 8][kNaiveBX + 8]>(lds));
             break;
     }
 }
 
-// LDS of the largest block (radius 4)
+// LDS of the largest block (radius 4): one plane buffer
 template <typename T>
 constexpr size_t naive_lds_bytes() { return sizeof(T) * (kNaiveBY + 8) * (kNaiveBX + 8); }
 

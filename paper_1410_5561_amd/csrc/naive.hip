@@ -9,16 +9,23 @@ namespace mwd {
 // One-dimensional grid over the blocks (bx fastest, then by, then bz).  Runs
 // of `patch` consecutive blocks (whole block rows) go to one XCD, so that a
 // block's x- and y-neighbours, whose halo rows and partial cache lines it
-// reads, mostly run at the same time on the same L2.
+// reads, mostly run at the same time on the same L2.  A 1024-thread block is
+// held to 64 registers per lane (two blocks per CU), except for the 25-point
+// variable stencil, whose 13 coefficient rings need more.
+template <int K, int BX, int BY>
+constexpr int naive_min_waves() { return (BX * BY >= 1024 && K != K25V) ? 8 : 1; }
+
 template <int K, typename T, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY)
+__global__ void __launch_bounds__(BX * BY, (naive_min_waves<K, BX, BY>()))
 naive_sweep_kernel(const T* __restrict__ src, T* __restrict__ dst, Weights<T> w,
                    int nx, int ny, int nz, long long sy, long long sz, int zchunk, int nbx, int nby, int patch)
 {
-    __shared__ T tile[BY + 2 * KindTraits<K>::R][BX + 2 * KindTraits<K>::R];
+    constexpr int PF = naive_prefetch<K, T>(false);
+    using G = NaiveGeom<K, BX, BY, PF>;
+    __shared__ T tile[G::NB][G::TY][G::TX];
     const int t = xcd_tile(blockIdx.x, gridDim.x, patch);
     const int r = t / nbx;
-    naive_block<K, T, BX, BY>(src, dst, w, nx, ny, nz, sy, sz, zchunk, t - r * nbx, r % nby, r / nby, tile);
+    naive_block<K, T, BX, BY, PF>(src, dst, w, nx, ny, nz, sy, sz, zchunk, t - r * nbx, r % nby, r / nby, tile);
 }
 
 template <int K, typename T>
@@ -27,6 +34,7 @@ static hipError_t launch_naive(const DevGrid& g, const HostWeights& hw, const vo
 {
     constexpr int R = KindTraits<K>::R;
     constexpr int BX = 64;
+    // radius 4: 16 rows (a block's threads also load its 2R(BX + BY) halo cells)
     constexpr int BY = (R == 1) ? 8 : 16;
     Weights<T> w;
     for (int m = 0; m < 13; ++m) {
