@@ -16,8 +16,10 @@
 // HBM access of a wave is a contiguous row segment.  A lane keeps, for each
 // time level, the 2R+1 most recent z-planes of its own (x, y) column in
 // registers (the z-neighbours), and publishes one plane per level per step to
-// an LDS exchange array that gives the x- and y-neighbours.  One workgroup
-// barrier per wavefront step; the exchange array is double-buffered.
+// an LDS exchange array that gives the y-neighbours and, except for radius-1
+// rows of one wave (whose x-neighbours move between lanes by DPP shifts), the
+// x-neighbours.  One workgroup barrier per wavefront step; the exchange array
+// is double-buffered.
 //
 // x tiles (Sec. III-A) run concurrently: each tile recomputes an R-wide ring
 // per remaining level around its x range (level tau spans x0 - (L - tau) R ..
@@ -86,6 +88,25 @@ __device__ __forceinline__ int opaque_uniform(int v)
 // An empty side effect: a branch around it stays a branch instead of
 // becoming per-lane selects.
 __device__ __forceinline__ void keep_branch() { asm volatile(""); }
+
+// Cross-lane moves of a wave (DPP wavefront shifts by one lane): lane i takes
+// lane i + 1's value (kDppFromAbove) or lane i - 1's (kDppFromBelow); the
+// lane with no source takes 0.  Every lane of the wave must be active.
+constexpr int kDppFromAbove = 0x130;  // wave_shl:1
+constexpr int kDppFromBelow = 0x138;  // wave_shr:1
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+        return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+}
 
 // Level sets of the diamond rows of a tile that no clipping touches (every
 // row inside the domain, every level inside 1 .. T).  Row yr of such a tile
@@ -559,15 +580,21 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         //     Where registers allow (radius 1 with at most 3 levels, or 7 in
         //     FP32), the in-plane neighbours of every level are read from
         //     LDS up front, so that the levels' chain does not wait on LDS
-        //     once per level.
+        //     once per level.  With one wave per diamond row at radius 1,
+        //     the x-neighbours come from the neighbouring lanes of the same
+        //     wave instead (a lane's own register holds the value it
+        //     published), by DPP shifts in wave-uniform control flow.
+        constexpr bool XDPP = R == 1 && WPR == 1;
         constexpr bool XYPF = R == 1 && (L <= 3 || (sizeof(T) == 4 && L <= 7));
         T xy[XYPF ? L + 1 : 1][4];
         if constexpr (XYPF) {
             if (UNMASKED || (xl >= R && xl < LX - R)) {
                 static_for<1, L + 1>([&](auto tc) MWD_INLINE {
                     constexpr int tau = decltype(tc)::value;
-                    xy[tau][0] = ex[eb][tau - 1][yr + R][xl + 1];
-                    xy[tau][1] = ex[eb][tau - 1][yr + R][xl - 1];
+                    if constexpr (!XDPP) {
+                        xy[tau][0] = ex[eb][tau - 1][yr + R][xl + 1];
+                        xy[tau][1] = ex[eb][tau - 1][yr + R][xl - 1];
+                    }
                     xy[tau][2] = ex[eb][tau - 1][yr + R + 1][xl];
                     xy[tau][3] = ex[eb][tau - 1][yr + R - 1][xl];
                 });
@@ -577,11 +604,22 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
             constexpr int tau = decltype(tc)::value;
             const int p = s - tau * R;
             if (((cm >> tau) & 1u) && (FAST || (p >= 0 && p < a.nz))) {
+                // the x-neighbours by lane shifts, before any per-lane branch
+                T xa = T(0), xb = T(0);
+                if constexpr (XDPP) {
+                    const T c = q[tau - 1][cmod(u - tau * R, Q)];
+                    xa = dpp_move<kDppFromAbove>(c);
+                    xb = dpp_move<kDppFromBelow>(c);
+                }
                 // a row type computes every lane: a lane outside the level's
                 // x range reads in-bounds LDS and its value is never read
                 if (UNMASKED || (xin && xl >= tau * R && xl < LX - tau * R)) {
                     auto nb = [&](int dx, int dy, int dz) MWD_INLINE -> T {
                         if (dz != 0) return q[tau - 1][cmod(u - tau * R + dz, Q)];
+                        if constexpr (XDPP) {
+                            if (dx > 0) return xa;
+                            if (dx < 0) return xb;
+                        }
                         if constexpr (XYPF) {
                             if (dx > 0) return xy[tau][0];
                             if (dx < 0) return xy[tau][1];
