@@ -111,12 +111,16 @@ static void fill_args(MwdArgs<T>& a, const DevGrid& d, const HostWeights& w, T* 
 
 template <typename T>
 static int build_graph(BatchGraph& bg, stencil_grid* grids, const HostWeights* hw, int n, int T_steps,
-                       int dtype, std::string* errmsg)
+                       int dtype, std::string* errmsg, const int* forced = nullptr)
 {
-    // 1. schedule per grid (autotuned per kind and size bucket): the batched
-    //    naive sweep (var -1) or a batched MWD shape
+    // 1. schedule per grid (autotuned per kind and size bucket, or forced):
+    //    the batched naive sweep (var -1) or a batched MWD shape
     std::vector<int> var(n);
     for (int i = 0; i < n; ++i) {
+        if (forced) {
+            var[i] = (forced[i] >= 0 && mwd_plane_ok(grids[i].sz, dtype)) ? forced[i] : -1;
+            continue;
+        }
         const TuneChoice c = tune_batch_choose(hw[i].kind, dtype, grids[i].nx, grids[i].ny, grids[i].nz, T_steps);
         // the tile kernel addresses a plane with 32-bit byte offsets
         if (c.mode == STENCIL_MODE_NAIVE || !mwd_plane_ok(grids[i].sz, dtype)) {
@@ -471,6 +475,75 @@ int batch_run(int plan_kind, int plan_dtype, BatchState** state, stencil_grid* g
     }
     for (int i = 0; i < n; ++i) grids[i].cur ^= (T & 1);
     return STENCIL_OK;
+}
+
+double batch_proxy_ms(int kind, int dtype, int nx, int ny, int nz, int T, int count, int var)
+{
+    const int h = radius_of(kind);
+    const size_t es = es_of(dtype);
+    const long long sy = nx + 2 * h, sz = sy * (ny + 2 * h);
+    const size_t bytes = ((size_t)sz * (size_t)(nz + 2 * h) * es + 255) & ~size_t(255);
+    const int narr = narr_of(kind);
+    const size_t total = (size_t)count * (size_t)(2 + narr) * bytes;
+    void* base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.0;
+    }
+    double ms = -1.0;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BatchGraph bg;
+    hipError_t e = hipMemset(base, 0, total);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        const long long off = (long long)h * sz + (long long)h * sy + h;
+        std::vector<stencil_grid> grids(count);
+        std::vector<HostWeights> hw(count);
+        for (int i = 0; i < count; ++i) {
+            char* gb = static_cast<char*>(base) + (size_t)i * (size_t)(2 + narr) * bytes;
+            stencil_grid& g = grids[i];
+            std::memset(&g, 0, sizeof(g));
+            g.nx = nx;
+            g.ny = ny;
+            g.nz = nz;
+            g.halo = h;
+            g.sy = sy;
+            g.sz = sz;
+            g.dtype = dtype;
+            g.cur = 0;
+            g.buf[0] = gb;
+            g.buf[1] = gb + bytes;
+            hw[i].kind = kind;
+            for (int m = 0; m < 13; ++m) {
+                hw[i].c[m] = 0.05;
+                hw[i].org[m] = m < narr ? gb + (2 + m) * bytes + off * es : nullptr;
+            }
+        }
+        std::vector<int> forced(count, var);
+        std::string msg;
+        const int rc = dtype == 0 ? build_graph<double>(bg, grids.data(), hw.data(), count, T, dtype, &msg, forced.data())
+                                  : build_graph<float>(bg, grids.data(), hw.data(), count, T, dtype, &msg, forced.data());
+        if (rc == STENCIL_OK) {
+            e = hipGraphLaunch(bg.exec, st);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            for (int r = 0; r < 2 && e == hipSuccess; ++r) e = hipGraphLaunch(bg.exec, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.f;
+            if (e == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / 2.0;
+        }
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    bg.release();
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(base);
+    (void)hipGetLastError();
+    return ms;
 }
 
 void batch_free(BatchState* s)

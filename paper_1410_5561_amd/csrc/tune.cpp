@@ -2,14 +2,16 @@
 // (diamond width, x lanes) by timing them on a proxy grid of the same x-y
 // extent, in the spirit of the paper's auto-tuning of diamond width,
 // frontlines and x-tile (Sec. II-A, Sec. IV-B).  The search space is pruned
-// to shapes whose tile kernel holds its working set in registers and LDS (a
-// shape that spills more than a few registers to scratch memory is not
-// tried), the analogue of keeping the cache block inside the cache
-// (Sec. III-B).  Each candidate's time for the whole run is predicted from a
-// few timed sweeps or diamond rows.  Choices are cached per device, stencil,
-// grid size and T for the life of the process and, if MWD_TUNE_CACHE names a
-// file, across processes.  MWD_TUNE_VERBOSE=1 prints every prediction to
-// stderr.
+// as the paper prunes it, by the cache block: a shape whose wavefront cache
+// block (Eq. 3 of Sec. III-B, with N_F = 1 and N_xb = lanes x element size)
+// exceeds half of a CU's on-chip storage (LDS plus registers; the model holds
+// while the block fills at most about half of the cache, Sec. IV-B) is not
+// tried, and neither is a shape whose compiled kernel spills more than a few
+// registers to scratch memory.  Each candidate's time for the whole run is
+// predicted from a few timed sweeps or diamond rows.  Choices are cached per
+// device, stencil, grid size and T for the life of the process and, if
+// MWD_TUNE_CACHE names a file, across processes.  MWD_TUNE_VERBOSE=1 prints
+// every pruning decision and every prediction to stderr.
 #include "tune.hpp"
 
 #include <cstdio>
@@ -23,6 +25,7 @@
 #include <vector>
 
 #include "../../include/mwd_stencil.h"
+#include "batch.hpp"
 #include "batch_variants.hpp"
 
 namespace mwd {
@@ -49,8 +52,26 @@ constexpr int kMinProxyNz = 64;
 // A tile kernel that spills more than this to scratch memory (bytes per lane)
 // is not tried; a few spilled registers outside the step loop cost little.
 constexpr size_t kMaxSpillBytes = 128;
-// factor on a batched MWD shape's proxy time (see tune_generic)
-constexpr double kBatchMwdPenalty = 2.0;
+// On-chip storage of one CU of gfx950: 160 KiB of LDS and a 512 KiB vector
+// register file.
+constexpr double kCuOnChipBytes = (160.0 + 512.0) * 1024.0;
+
+// Eq. (3): the wavefront cache block in bytes,
+// N_xb [N_D Dw (Dw/2 - R + N_F) + 2R (Dw + W_w)], W_w = Dw - 2R + N_F.
+double cache_block_bytes(int kind, int dtype, const MwdShape& s)
+{
+    const double R = radius_of(kind), ND = ndomain_of(kind), Dw = s.dw, NF = 1.0;
+    const double Nxb = (double)s.lanes() * (dtype == 0 ? 8.0 : 4.0);
+    const double Ww = Dw - 2.0 * R + NF;
+    return Nxb * (ND * Dw * (Dw / 2.0 - R + NF) + 2.0 * R * (Dw + Ww));
+}
+
+
+bool tune_verbose()
+{
+    const char* ve = std::getenv("MWD_TUNE_VERBOSE");
+    return ve && *ve && *ve != '0';
+}
 
 const char* cache_path()
 {
@@ -226,30 +247,63 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, int batch, 
         *out = it->second;
         return STENCIL_OK;
     }
-    // candidates
+    // candidates (for a batch also the index of the batched tile variant)
     std::vector<TuneChoice> cands;
+    std::vector<int> cand_var;
     if (batch) {
         // batch 1: the batched naive sweep or a batched MWD shape; 2: MWD only
-        if (batch == 1) cands.push_back(TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}});
+        if (batch == 1) {
+            cands.push_back(TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}});
+            cand_var.push_back(-1);
+        }
         const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
         for (int i = 0; i < nv; ++i)
-            if (kBatchVariantInfo[i].kind == kind)
+            if (kBatchVariantInfo[i].kind == kind) {
                 cands.push_back(TuneChoice{STENCIL_MODE_MWD, MwdShape{kBatchVariantInfo[i].dw, kBatchVariantInfo[i].wpr}});
+                cand_var.push_back(i);
+            }
     } else {
         cands.push_back(TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}});
         MwdShape shapes[16];
         const int ns = mwd_shapes(kind, dtype, shapes, 16);
         for (int i = 0; i < ns; ++i) {
             size_t scratch = 0;
-            if (mwd_kernel_scratch(kind, dtype, shapes[i], &scratch) == hipSuccess && scratch <= kMaxSpillBytes)
-                cands.push_back(TuneChoice{STENCIL_MODE_MWD, shapes[i]});
+            const bool spill_ok =
+                mwd_kernel_scratch(kind, dtype, shapes[i], &scratch) == hipSuccess && scratch <= kMaxSpillBytes;
+            const double cs = cache_block_bytes(kind, dtype, shapes[i]);
+            const bool cs_ok = cs <= 0.5 * kCuOnChipBytes;
+            if (tune_verbose())
+                std::fprintf(stderr, "[mwd tune] kind %d dtype %d dw %d lanes %d: cache block (Eq. 3) %.1f KiB of "
+                             "%.0f KiB on chip, spill %zu B/lane: %s\n", kind, dtype, shapes[i].dw,
+                             shapes[i].lanes(), cs / 1024.0, kCuOnChipBytes / 1024.0, scratch,
+                             !cs_ok ? "pruned (cache block above half the on-chip storage)"
+                                    : !spill_ok ? "pruned (register spill)" : "candidate");
+            if (spill_ok && cs_ok) cands.push_back(TuneChoice{STENCIL_MODE_MWD, shapes[i]});
         }
     }
     if (cands.empty()) return STENCIL_EUNSUPPORTED;
     TuneChoice best = cands[0];
-    const char* ve = std::getenv("MWD_TUNE_VERBOSE");
-    const bool verbose = ve && *ve && *ve != '0';
-    if (cands.size() > 1) {
+    const bool verbose = tune_verbose();
+    if (cands.size() > 1 && batch) {
+        // the batched graph itself, timed on a proxy batch of copies of this
+        // bucket's grid (as many as make about 2^26 points, 2 to 64 grids)
+        const long long pts = std::max(1LL, (long long)nx * ny * nz);
+        const int count = (int)std::max(2LL, std::min(64LL, (1LL << 26) / pts));
+        double best_per = -1.0;
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const TuneChoice& c = cands[ci];
+            const double ms = batch_proxy_ms(kind, dtype, nx, ny, nz, T, count, cand_var[ci]);
+            if (verbose)
+                std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d T=%d (batched proxy: %d grids): %s dw %d "
+                             "lanes %d: %.3f ms, %.2f GLUP/s\n", kind, dtype, nx, ny, nz, T, count,
+                             c.mode == STENCIL_MODE_NAIVE ? "naive" : "mwd", c.shape.dw, c.shape.wpr * 64, ms,
+                             ms > 0 ? (double)count * pts * T / (ms * 1e6) : 0.0);
+            if (ms > 0 && (best_per < 0 || ms < best_per)) {
+                best_per = ms;
+                best = c;
+            }
+        }
+    } else if (cands.size() > 1) {
         // proxy: the same x-y extent, and as many planes as fit the budget
         const int h = radius_of(kind);
         const size_t es = dtype == 0 ? 8 : 4;
@@ -262,21 +316,12 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, int batch, 
         double best_ms = -1.0;
         if (make_proxy(P, kind, dtype, nx, ny, nzp) && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess) {
             for (const TuneChoice& c : cands) {
-                // a batched shape is timed through the row kernel of the same tile
-                if (c.mode == STENCIL_MODE_MWD && !mwd_supported(kind, dtype, c.shape)) continue;
-                double ms = predict_ms(P, T, nz, c, s);
-                // The proxy times a batched MWD shape through the single-grid
-                // row kernel; in the batch the shape runs inside the shared
-                // 1024-thread kernel (fewer registers per lane) and in row
-                // groups that wait for every grid's previous row, which the
-                // proxy does not see (on 256 mixed 7c/25c grids, all grids
-                // on MWD ran 2.8x slower than all grids naive).  So in a batch
-                // MWD must win the proxy by 2x.
-                if (batch == 1 && c.mode == STENCIL_MODE_MWD && ms > 0) ms *= kBatchMwdPenalty;
+                const double ms = predict_ms(P, T, nz, c, s);
                 if (verbose)
-                    std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d (proxy %d planes) T=%d%s: %s dw %d lanes %d: %.3f ms\n",
-                                 kind, dtype, nx, ny, nz, nzp, T, batch ? " (batched)" : "",
-                                 c.mode == STENCIL_MODE_NAIVE ? "naive" : "mwd", c.shape.dw, c.shape.wpr * 64, ms);
+                    std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d (proxy %d planes) T=%d: %s dw %d "
+                                 "lanes %d: predicted %.3f ms, %.2f GLUP/s\n", kind, dtype, nx, ny, nz, nzp, T,
+                                 c.mode == STENCIL_MODE_NAIVE ? "naive" : "mwd", c.shape.dw, c.shape.wpr * 64, ms,
+                                 ms > 0 ? (double)nx * ny * nz * T / (ms * 1e6) : 0.0);
                 if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
                     best_ms = ms;
                     best = c;
@@ -286,6 +331,10 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, int batch, 
         }
         (void)hipGetLastError();
     }
+    if (verbose)
+        std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%dx%d T=%d%s: chose %s dw %d lanes %d\n", kind, dtype,
+                     nx, ny, nz, T, batch ? " (batched)" : "", best.mode == STENCIL_MODE_NAIVE ? "naive" : "mwd",
+                     best.shape.dw, best.shape.wpr * 64);
     g_cache[key] = best;
     save_entry(key, best);
     *out = best;
