@@ -51,6 +51,9 @@ def parse():
                     help="skip the other workloads (4 in FP32, 3 in FP64 and FP32, 5) that the "
                          "default line reports beside the headline workload")
     ap.add_argument("--extra-steps", type=int, default=3, help="timed steps of each other workload")
+    ap.add_argument("--energy-sweep", action="store_true",
+                    help="energy to solution of the naive sweep and every MWD diamond width on the "
+                         "workload's grid, in FP64 and FP32 (GPU socket energy counter)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -299,6 +302,52 @@ def bench_batch(a, torch, S):
     return 0
 
 
+def energy_sweep(a, torch, S, windex):
+    """Energy to solution per lattice-site update against the code balance:
+    the naive sweep and each MWD tile shape, FP64 and FP32, on one workload's
+    grid (the counterpart of the energy tables and the energy-vs-code-balance
+    figure of Sec. IV-C).  Each point: three windows of >= 1.5 s of repeated
+    whole runs; the median window."""
+    import gridgen
+    from paper_1410_5561_amd import energy
+    w = gridgen.workloads()[windex]
+    kind, n, T = w["kind"], w["n"], w["T"]
+    R = gridgen.RADIUS[kind]
+    shapes = {1: [("naive", 0, 0), ("mwd", 4, 64), ("mwd", 4, 128), ("mwd", 4, 256), ("mwd", 8, 64),
+                  ("mwd", 8, 128)],
+              4: [("naive", 0, 0), ("mwd", 8, 64), ("mwd", 8, 128), ("mwd", 16, 64)]}[R]
+    meter = energy.EnergyMeter()
+    out = {"workload": w["name"], "meter": "AMD SMI energy counter of the GPU socket", "points": []}
+    if not meter.ok:
+        out["error"] = meter.error
+        return out
+    for dtype in ("f64", "f32"):
+        u0, co = make_inputs(w, dtype, windex)
+        u0_dev = torch.from_numpy(u0).cuda()
+        co_dev = co if kind in ("7c", "25c") else [torch.from_numpy(c).cuda() for c in co]
+        del u0, co
+        for mode, dw, lanes in shapes:
+            try:
+                sec, _, desc, _, st = time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, 2, 1, mode,
+                                                dw, lanes, R, meter=meter)
+            except Exception as e:  # a shape not compiled for this dtype
+                out["points"].append({"dtype": dtype, "mode": mode, "dw": dw, "lanes": lanes,
+                                      "error": str(e)[:80]})
+                continue
+            del st
+            en = desc.get("energy") or {}
+            out["points"].append({"dtype": dtype, "mode": mode, "dw": dw, "lanes": lanes,
+                                  "model_bytes_per_lup": round(desc["model_bytes_per_lup"], 3),
+                                  "GLUP_per_s": en.get("GLUP_per_s"), "pJ_per_LUP": en.get("pJ_per_LUP"),
+                                  "avg_power_W": en.get("avg_power_W"),
+                                  "pJ_per_LUP_windows": en.get("pJ_per_LUP_windows")})
+            log(a, "energy point", out["points"][-1])
+        del u0_dev, co_dev
+        torch.cuda.empty_cache()
+    meter.close()
+    return out
+
+
 def other_workload(a, torch, S, windex, dtype):
     """A compact line for one more workload: the autotuned plan against the
     naive sweep, both timed over whole runs with inputs resident."""
@@ -489,6 +538,13 @@ def main():
                       "ms_per_step": round(bsec * 1e3 / a.extra_steps, 3), "grids": bn})
         out["other_workloads"] = extra
         torch.cuda.empty_cache()
+    if a.energy_sweep:
+        if state is not None:
+            del state
+            state = None
+        u0_dev = co_dev = None
+        torch.cuda.empty_cache()
+        out["energy_sweep"] = energy_sweep(a, torch, S, a.workload)
     # practical bandwidth reference: streaming copy of 2 GiB
     nbytes = 1 << 31
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -143,9 +143,8 @@ int stencil_destroy(stencil_plan *plan);
 /* Advance n independent grids (1 <= n <= 65535; uneven sizes, any kind; one
  * dtype per call) by T steps with ONE hipGraph launch (batched form of the
  * MWD method, Sec. II-A).  Per grid the plan picks, by kind and size bucket
- * (autotuned once; a batched MWD shape must beat the naive sweep by 2x on its
- * single-grid proxy, which does not see the batch's shared kernel and row
- * groups), either:
+ * (autotuned once per bucket: the batched graph itself is timed on a proxy
+ * batch of copies of the bucket's grid, once per candidate schedule), either:
  *  - MWD tiles: the tiles of all such grids are grouped by diamond row, one
  *    kernel launch per group (a workgroup per tile, any grid), then a gather;
  *    kernel boundaries are the row-to-row dependencies.  Shapes: 7c and 25c
@@ -195,6 +194,14 @@ int stencil_diff_norms(const stencil_grid *a, const stencil_grid *b, double out[
  * one device share the array and race: order them (one stream, or events).
  * Errors: EINVAL (as stencil_norms, or out_dev NULL or misaligned), EDEVICE. */
 int stencil_norms_noalloc(const stencil_grid *grid, int32_t which, double *out_dev, void *stream);
+
+/* On-chip resources of the compiled MWD tile kernel of a shape (Dw, lanes),
+ * for comparing its working set with the cache-block model (Eq. 3 of
+ * Sec. III-B): out[0] = vector registers per lane, out[1] = LDS bytes per
+ * workgroup, out[2] = register-spill (scratch) bytes per lane, out[3] =
+ * threads per workgroup, out[4] = workgroups that fit one CU.  Needs a GPU.
+ * Errors: EINVAL, EUNSUPPORTED (no kernel for the shape), EDEVICE. */
+int stencil_kernel_resources(int32_t kind, int32_t dtype, int32_t dw, int32_t lanes, int32_t out[5]);
 
 /* Describe a plan's chosen schedule (after the first run for autotuned plans). */
 int stencil_plan_describe(const stencil_plan *plan, stencil_plan_desc *out);

@@ -17,7 +17,7 @@ __all__ = [
     "stencil_norms", "stencil_norms_noalloc", "stencil_diff_norms", "stencil_plan_describe",
     "stencil_model_bytes_per_lup", "stencil_strerror", "stencil_last_error",
     "stencil_abi_version", "stencil_profile_enable", "stencil_profile_read",
-    "stencil_stream_copy", "Plan", "make_grid", "make_coeffs", "padded_empty", "radius",
+    "stencil_stream_copy", "stencil_kernel_resources", "Plan", "make_grid", "make_coeffs", "padded_empty", "radius",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -81,6 +81,8 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "stencil_norms_noalloc": (ctypes.c_int, [ctypes.POINTER(StencilGrid), ctypes.c_int32, ctypes.c_void_p,
                                              ctypes.c_void_p]),
+    "stencil_kernel_resources": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_int32)]),
     "stencil_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StencilPlanDesc)]),
     "stencil_model_bytes_per_lup": (ctypes.c_double, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "stencil_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -213,6 +215,14 @@ def stencil_profile_read(plan) -> dict:
 def stencil_stream_copy(dst, src, nbytes: int, stream=None):
     _check(lib().stencil_stream_copy(ctypes.c_void_p(dst), ctypes.c_void_p(src), int(nbytes),
                                      _stream_ptr(stream)), "stencil_stream_copy")
+
+
+def stencil_kernel_resources(kind: str, dtype: str, dw: int, lanes: int) -> dict:
+    out = (ctypes.c_int32 * 5)()
+    _check(lib().stencil_kernel_resources(KIND[kind], DTYPE[dtype], int(dw), int(lanes), out),
+           "stencil_kernel_resources")
+    return {"vgprs": out[0], "lds_bytes": out[1], "scratch_bytes_per_lane": out[2],
+            "threads": out[3], "workgroups_per_cu": out[4]}
 
 
 def stencil_plan_describe(plan) -> dict:

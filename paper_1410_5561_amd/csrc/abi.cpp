@@ -435,6 +435,20 @@ int stencil_run_batched(stencil_plan* p, stencil_grid* grids, const stencil_coef
     return rc;
 }
 
+int stencil_kernel_resources(int32_t kind, int32_t dtype, int32_t dw, int32_t lanes, int32_t out[5])
+{
+    if (!kind_ok(kind) || (dtype != STENCIL_F64 && dtype != STENCIL_F32) || !out)
+        return fail(STENCIL_EINVAL, "bad kind, dtype or out");
+    if (lanes <= 0 || lanes % 64) return fail(STENCIL_EINVAL, "lanes must be a positive multiple of 64");
+    const MwdShape s{dw, lanes / 64};
+    if (!mwd_supported(kind, dtype, s)) return fail(STENCIL_EUNSUPPORTED, "no MWD kernel for this shape");
+    int r[5];
+    hipError_t e = mwd_kernel_resources(kind, dtype, s, r);
+    if (e != hipSuccess) return hip_fail(e, "kernel attributes");
+    for (int i = 0; i < 5; ++i) out[i] = r[i];
+    return STENCIL_OK;
+}
+
 int stencil_norms_noalloc(const stencil_grid* g, int32_t which, double* out_dev, void* stream)
 {
     int rc = check_grid(g, "grid");

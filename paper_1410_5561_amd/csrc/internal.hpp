@@ -102,6 +102,9 @@ int mwd_levels(int kind, const MwdShape& s);
 int mwd_shapes(int kind, int dtype, MwdShape* out, int cap);
 // Whether the shape's row kernel keeps values in scratch memory (register spill).
 hipError_t mwd_kernel_scratch(int kind, int dtype, const MwdShape& s, size_t* bytes_per_lane);
+// The shape's row kernel: VGPRs per lane, LDS bytes, scratch bytes per lane,
+// threads per workgroup, workgroups per CU.
+hipError_t mwd_kernel_resources(int kind, int dtype, const MwdShape& s, int out[5]);
 int mwd_xtile(int kind, const MwdShape& s);
 
 // Run T steps with MWD.  `scratch` holds two extra grid-sized buffer pairs

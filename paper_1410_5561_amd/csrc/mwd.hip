@@ -59,6 +59,24 @@ hipError_t mwd_kernel_scratch(int kind, int dtype, const MwdShape& s, size_t* by
     return hipSuccess;
 }
 
+hipError_t mwd_kernel_resources(int kind, int dtype, const MwdShape& s, int out[5])
+{
+    const MwdEntry* e = find_entry(kind, dtype, s);
+    if (!e) return hipErrorInvalidValue;
+    hipFuncAttributes fa;
+    hipError_t err = hipFuncGetAttributes(&fa, e->kernel);
+    if (err != hipSuccess) return err;
+    int per_cu = 0;
+    err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->kernel, 64 * s.dw * s.wpr, 0);
+    if (err != hipSuccess) return err;
+    out[0] = fa.numRegs;
+    out[1] = (int)fa.sharedSizeBytes;
+    out[2] = (int)fa.localSizeBytes;
+    out[3] = 64 * s.dw * s.wpr;
+    out[4] = per_cu;
+    return hipSuccess;
+}
+
 int mwd_levels(int kind, const MwdShape& s) { return s.dw / radius_of(kind) - 1; }
 
 int mwd_xtile(int kind, const MwdShape& s) { return 64 * s.wpr - 2 * mwd_levels(kind, s) * radius_of(kind); }

@@ -14,6 +14,12 @@ matches the sources.
         --kernel mwd_row_kernel --workload NAME --dtype f64 --shape 8x64 \\
         --model-bytes-per-launch B --copy-bytes N --out profiles/FILE.txt \\
         --cmd-trace "..." --cmd-fetch "..." --cmd-write "..."
+
+SQ-counter summaries (instruction mix, wait fractions, LDS bank conflicts, L2
+hit rate) of one kernel from one or more `rocprofv3 --pmc` runs:
+
+    python -m paper_1410_5561_amd.profiling sq --pmc DIR [DIR ...] --kernel K \\
+        --workload NAME --dtype f32 --shape naive --cmd "..." [--cmd "..."] --out FILE
 """
 from __future__ import annotations
 
@@ -127,7 +133,75 @@ def traffic_for(kernel, workload, dtype, shape):
     return float(s["traffic_bytes_per_launch"])
 
 
+def sq_counters(pmc_dirs, match):
+    """{counter: average per dispatch} over every --pmc run directory given,
+    for the kernels whose name contains `match`; and the dispatch count."""
+    vals, ndisp = {}, 0
+    for d in pmc_dirs:
+        per = defaultdict(lambda: defaultdict(float))
+        for p in _csvs(d, "counter_collection.csv"):
+            with open(p, newline="") as f:
+                for r in csv.DictReader(f):
+                    if match in r.get("Kernel_Name", ""):
+                        per[r["Counter_Name"]][(p, r["Dispatch_Id"])] += float(r["Counter_Value"])
+        for c, dd in per.items():
+            vals[c] = sum(dd.values()) / len(dd)
+            ndisp = max(ndisp, len(dd))
+    return vals, ndisp
+
+
+def sq_summary_lines(vals, ndisp, kernel, workload, dtype, shape, cmds):
+    """Key: value lines of an SQ-counter summary with the derived ratios."""
+    lines = ["# rocprofv3 SQ counters: %s, workload %s, %s, shape %s" % (kernel, workload, dtype, shape)]
+    lines += ["# run: %s" % c for c in cmds]
+    lines += ["# values are averages per dispatch of the kernel; wave-cycles are summed over waves",
+              "kernel: %s" % kernel, "workload: %s" % workload, "dtype: %s" % dtype, "shape: %s" % shape,
+              "source_hash: %s" % source_hash(kernel), "dispatches: %d" % ndisp]
+    for c in sorted(vals):
+        lines.append("%s: %.1f" % (c, vals[c]))
+
+    def ratio(name, num, den):
+        if num in vals and den in vals and vals[den]:
+            lines.append("%s: %.4f" % (name, vals[num] / vals[den]))
+
+    ratio("wait_inst_any_over_wave_cycles", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES")
+    ratio("wait_any_over_wave_cycles", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES")
+    ratio("lds_bank_conflict_over_lds_active", "SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS")
+    if "TCC_HIT_sum" in vals and "TCC_MISS_sum" in vals:
+        tot = vals["TCC_HIT_sum"] + vals["TCC_MISS_sum"]
+        if tot:
+            lines.append("l2_hit_rate: %.4f" % (vals["TCC_HIT_sum"] / tot))
+    if vals.get("SQ_WAVES"):
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR"):
+            if c in vals:
+                lines.append("%s_per_wave: %.1f" % (c.lower(), vals[c] / vals["SQ_WAVES"]))
+    return lines
+
+
+def sq_main(argv):
+    ap = argparse.ArgumentParser(description="Summary of SQ (and L2) counter runs of one kernel.")
+    ap.add_argument("--pmc", nargs="+", required=True, help="one directory per rocprofv3 --pmc run")
+    ap.add_argument("--kernel", required=True, choices=sorted(_KERNEL_SOURCES))
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--dtype", required=True)
+    ap.add_argument("--shape", required=True)
+    ap.add_argument("--cmd", action="append", required=True, help="the command of each run, in order")
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    vals, ndisp = sq_counters(a.pmc, a.kernel)
+    lines = sq_summary_lines(vals, ndisp, a.kernel, a.workload, a.dtype, a.shape, a.cmd)
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
 def main(argv=None):
+    import sys
+    argv = sys.argv[1:] if argv is None else argv
+    if argv and argv[0] == "sq":
+        return sq_main(argv[1:])
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)

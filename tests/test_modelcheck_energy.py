@@ -127,3 +127,18 @@ def test_energy_meter_without_device_reports_error():
     if not m.ok:
         assert m.error
     m.close()
+
+
+def test_cacheblock_tool_matches_the_worked_example_and_radius4_values():
+    """The cache-block table's Eq. (3) against the worked example (R = 1) and the
+    hand-evaluated radius-4 values kept in tests/golden/."""
+    import json
+    from paper_1410_5561_amd import cacheblock
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g1 = json.load(open(os.path.join(here, "cache_block_example.json")))
+    kind = "7c"  # N_D = 2, R = 1 as in the example
+    assert cacheblock.cache_block(kind, 8, g1["Dw"], 1, nf=g1["N_F"]) == 8 * g1["C_S_per_Nxb"]
+    g4 = json.load(open(os.path.join(here, "cache_block_r4.json")))
+    for c in g4["cases"]:
+        k = {2: "25c", 15: "25v"}[c["N_D"]]
+        assert cacheblock.cache_block(k, 4, c["Dw"], 32, nf=c["N_F"]) == 128 * c["C_S_per_Nxb"]

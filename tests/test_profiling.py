@@ -74,3 +74,27 @@ def test_summary_scales_by_copy_kernel_and_gates_on_source_hash(tmp_path, monkey
         f.write(text.replace("source_hash: " + s["source_hash"], "source_hash: 0000"))
     assert profiling.traffic_for("mwd_row_kernel", "wl^1", "f64", "8x64") is None
     assert profiling.traffic_for("mwd_row_kernel", "other", "f64", "8x64") is None
+
+
+def test_sq_summary_averages_and_ratios(tmp_path):
+    """SQ counters from two --pmc runs: per-dispatch averages (counters of one
+    dispatch split over rows are summed), wait fractions, the L2 hit rate and
+    per-wave instruction counts."""
+    k = "void mwd::naive_sweep_kernel<2, float, 64, 16>(float const*, float*)"
+    other = "mwd::stream_copy_kernel(u32x4*, u32x4 const*, long long)"
+    hdr = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write(str(tmp_path / "a" / "h" / "1_counter_collection.csv"), hdr,
+           [[1, k, "SQ_WAVES", 100], [1, k, "SQ_WAVE_CYCLES", 600], [1, k, "SQ_WAVE_CYCLES", 400],
+            [1, k, "SQ_WAIT_INST_ANY", 250], [2, k, "SQ_WAVES", 100], [2, k, "SQ_WAVE_CYCLES", 1000],
+            [2, k, "SQ_WAIT_INST_ANY", 250], [1, k, "SQ_INSTS_VALU", 5000], [2, k, "SQ_INSTS_VALU", 5000],
+            [3, other, "SQ_WAVES", 7]])
+    _write(str(tmp_path / "b" / "h" / "2_counter_collection.csv"), hdr,
+           [[1, k, "TCC_HIT_sum", 30], [1, k, "TCC_MISS_sum", 70]])
+    vals, n = profiling.sq_counters([str(tmp_path / "a"), str(tmp_path / "b")], "naive_sweep_kernel")
+    assert n == 2 and vals["SQ_WAVES"] == 100 and vals["SQ_WAVE_CYCLES"] == 1000
+    lines = profiling.sq_summary_lines(vals, n, "naive_sweep_kernel", "w", "f32", "naive", ["cmd a", "cmd b"])
+    d = dict(l.split(": ", 1) for l in lines if not l.startswith("#"))
+    assert float(d["wait_inst_any_over_wave_cycles"]) == 0.25
+    assert float(d["l2_hit_rate"]) == 0.3
+    assert float(d["sq_insts_valu_per_wave"]) == 50.0
+    assert "# run: cmd b" in lines
