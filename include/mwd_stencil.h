@@ -212,6 +212,14 @@ int stencil_plan_describe(const stencil_plan *plan, stencil_plan_desc *out);
  * arguments. */
 double stencil_model_bytes_per_lup(int32_t kind, int32_t dtype, int32_t dw);
 
+/* Wavefront cache block in bytes: Eq. (3) of Sec. III-B,
+ * N_xb [N_D Dw (Dw/2 - R + N_F) + 2R (Dw + W_w)], W_w = Dw - 2R + N_F, for
+ * diamond width dw, nf frontlines (N_F) and an x extent of `lanes` elements
+ * (N_xb = lanes x element size).  The autotuner tries a tile shape only if
+ * its block (nf = 1) fills at most half of a CU's LDS and registers.
+ * Negative on bad arguments. */
+double stencil_model_cache_block(int32_t kind, int32_t dtype, int32_t dw, int32_t lanes, int32_t nf);
+
 /* Kernel timing for measurement tools.  While enabled, the plan records a HIP
  * event pair on the run's stream around every kernel it launches.
  * stencil_profile_read waits for those events and returns

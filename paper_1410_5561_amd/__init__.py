@@ -15,7 +15,7 @@ __all__ = [
     "KIND", "DTYPE", "MODE", "StencilError", "lib", "lib_path",
     "stencil_create", "stencil_run", "stencil_destroy", "stencil_run_batched",
     "stencil_norms", "stencil_norms_noalloc", "stencil_diff_norms", "stencil_plan_describe",
-    "stencil_model_bytes_per_lup", "stencil_strerror", "stencil_last_error",
+    "stencil_model_bytes_per_lup", "stencil_model_cache_block", "stencil_strerror", "stencil_last_error",
     "stencil_abi_version", "stencil_profile_enable", "stencil_profile_read",
     "stencil_stream_copy", "stencil_kernel_resources", "Plan", "make_grid", "make_coeffs", "padded_empty", "radius",
 ]
@@ -85,6 +85,8 @@ _SIGS = {
                                                 ctypes.POINTER(ctypes.c_int32)]),
     "stencil_plan_describe": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StencilPlanDesc)]),
     "stencil_model_bytes_per_lup": (ctypes.c_double, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "stencil_model_cache_block": (ctypes.c_double, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_int32, ctypes.c_int32]),
     "stencil_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stencil_last_error": (ctypes.c_char_p, []),
     "stencil_abi_version": (ctypes.c_int, []),
@@ -148,6 +150,10 @@ def stencil_last_error() -> str:
 
 def stencil_model_bytes_per_lup(kind: str, dtype: str, dw: int) -> float:
     return lib().stencil_model_bytes_per_lup(KIND[kind], DTYPE[dtype], int(dw))
+
+
+def stencil_model_cache_block(kind: str, dtype: str, dw: int, lanes: int, nf: int = 1) -> float:
+    return lib().stencil_model_cache_block(KIND[kind], DTYPE[dtype], int(dw), int(lanes), int(nf))
 
 
 def stencil_create(kind: str, dtype: str, nx: int, ny: int, nz: int, mode: str | None = None,

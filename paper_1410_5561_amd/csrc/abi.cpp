@@ -216,6 +216,13 @@ double stencil_model_bytes_per_lup(int32_t kind, int32_t dtype, int32_t dw)
     return s * 2.0 * R * ((2.0 * dw - 2.0 * R) + (ND * dw + 2.0 * R)) / ((double)dw * dw);
 }
 
+double stencil_model_cache_block(int32_t kind, int32_t dtype, int32_t dw, int32_t lanes, int32_t nf)
+{
+    if (!kind_ok(kind) || (dtype != STENCIL_F64 && dtype != STENCIL_F32) || dw < 1 || lanes < 1 || nf < 1)
+        return -1.0;
+    return cache_block_model(kind, dtype, dw, lanes, nf);
+}
+
 int stencil_create(stencil_plan** out, int32_t kind, int32_t dtype, int32_t nx, int32_t ny, int32_t nz,
                    const stencil_params* p)
 {

@@ -30,6 +30,14 @@
 
 namespace mwd {
 
+double cache_block_model(int kind, int dtype, int dw, int lanes, int nf)
+{
+    const double R = radius_of(kind), ND = ndomain_of(kind), Dw = dw, NF = nf;
+    const double Nxb = (double)lanes * (dtype == 0 ? 8.0 : 4.0);
+    const double Ww = Dw - 2.0 * R + NF;
+    return Nxb * (ND * Dw * (Dw / 2.0 - R + NF) + 2.0 * R * (Dw + Ww));
+}
+
 MwdShape default_shape(int kind, int dtype)
 {
     if (kind == K25C || kind == K25V) return MwdShape{16, 1};
@@ -56,14 +64,9 @@ constexpr size_t kMaxSpillBytes = 128;
 // register file.
 constexpr double kCuOnChipBytes = (160.0 + 512.0) * 1024.0;
 
-// Eq. (3): the wavefront cache block in bytes,
-// N_xb [N_D Dw (Dw/2 - R + N_F) + 2R (Dw + W_w)], W_w = Dw - 2R + N_F.
 double cache_block_bytes(int kind, int dtype, const MwdShape& s)
 {
-    const double R = radius_of(kind), ND = ndomain_of(kind), Dw = s.dw, NF = 1.0;
-    const double Nxb = (double)s.lanes() * (dtype == 0 ? 8.0 : 4.0);
-    const double Ww = Dw - 2.0 * R + NF;
-    return Nxb * (ND * Dw * (Dw / 2.0 - R + NF) + 2.0 * R * (Dw + Ww));
+    return mwd::cache_block_model(kind, dtype, s.dw, s.lanes(), 1);
 }
 
 

@@ -10,6 +10,11 @@ struct TuneChoice {
     MwdShape shape;  // valid for MWD
 };
 
+// Eq. (3) of Sec. III-B: the wavefront cache block in bytes for diamond
+// width dw, nf frontlines and an x extent of `lanes` elements,
+// N_xb [N_D Dw (Dw/2 - R + N_F) + 2R (Dw + W_w)], W_w = Dw - 2R + N_F.
+double cache_block_model(int kind, int dtype, int dw, int lanes, int nf);
+
 // A shape that fits every supported size of this (kind, dtype).
 MwdShape default_shape(int kind, int dtype);
 

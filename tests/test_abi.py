@@ -157,3 +157,18 @@ def test_destroy_without_runs_needs_no_device(L):
     rc, p = _rc_create(L, 2, 1, 16, 16, 16, S.StencilParams(2, 16, 64, 0))
     assert rc == 0
     assert L.stencil_destroy(p) == 0
+
+
+def test_model_cache_block_golden(L):
+    """The library's Eq. (3) (the tuner's pruning model) against the worked
+    example of Sec. III-B and the hand-evaluated radius-4 values."""
+    import json
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    g1 = json.load(open(os.path.join(here, "cache_block_example.json")))
+    # N_D = 2, R = 1: the 7-point constant stencil; N_xb = 8 bytes per lane
+    assert S.stencil_model_cache_block("7c", "f64", g1["Dw"], 1, g1["N_F"]) == 8 * g1["C_S_per_Nxb"]
+    for c in json.load(open(os.path.join(here, "cache_block_r4.json")))["cases"]:
+        kind = {2: "25c", 15: "25v"}[c["N_D"]]
+        assert S.stencil_model_cache_block(kind, "f32", c["Dw"], 32, c["N_F"]) == 128 * c["C_S_per_Nxb"]
+    assert L.stencil_model_cache_block(9, 0, 8, 64, 1) < 0
+    assert L.stencil_model_cache_block(0, 0, 8, 0, 1) < 0
