@@ -65,6 +65,7 @@ class StencilError(RuntimeError):
 
 
 _lib = None
+ABI_VERSION = 1  # the structs below match this version of include/mwd_stencil.h
 _SIGS = {
     "stencil_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -109,6 +110,9 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.stencil_abi_version() != ABI_VERSION:
+            raise RuntimeError("libmwdstencil.so has ABI %d, this binding needs %d: rebuild it"
+                               % (L.stencil_abi_version(), ABI_VERSION))
         _lib = L
     return _lib
 
@@ -280,9 +284,11 @@ def padded_empty(nx, ny, nz, halo, dtype, device="cuda"):
     return torch.empty((nz + 2 * halo, ny + 2 * halo, nx + 2 * halo), dtype=td, device=device)
 
 
-def make_grid(a, b, halo: int, cur: int = 0) -> StencilGrid:
-    """Describe two padded, contiguous CUDA tensors of shape
-    (nz + 2h, ny + 2h, nx + 2h) as a stencil_grid (buf[0] = a, buf[1] = b)."""
+def make_grid(a, b, halo: int, cur: int = 0, nx: int | None = None, lead: int = 0) -> StencilGrid:
+    """Describe two contiguous CUDA tensors of shape (nz + 2h, ny + 2h, W) as a
+    stencil_grid (buf[0] = a, buf[1] = b).  Each row holds the padded x extent
+    nx + 2h starting at column `lead`; by default nx = W - 2h - lead (rows
+    without padding).  sy = W and sz = W (ny + 2h) are the tensors' strides."""
     import torch
     if a.shape != b.shape or a.dtype != b.dtype:
         raise ValueError("both buffers need the same shape and dtype")
@@ -290,18 +296,25 @@ def make_grid(a, b, halo: int, cur: int = 0) -> StencilGrid:
         raise ValueError("buffers must be contiguous")
     if a.dtype not in (torch.float64, torch.float32):
         raise ValueError("dtype must be float64 or float32")
-    nzp, nyp, nxp = a.shape
+    nzp, nyp, width = a.shape
+    if nx is None:
+        nx = width - 2 * halo - lead
+    if lead < 0 or nx < 1 or lead + nx + 2 * halo > width:
+        raise ValueError("rows of %d elements cannot hold %d + 2 x %d from column %d" % (width, nx, halo, lead))
     g = StencilGrid()
-    g.nx, g.ny, g.nz, g.halo = nxp - 2 * halo, nyp - 2 * halo, nzp - 2 * halo, halo
+    g.nx, g.ny, g.nz, g.halo = nx, nyp - 2 * halo, nzp - 2 * halo, halo
     g.sy, g.sz = a.stride(1), a.stride(0)
     g.dtype = 0 if a.dtype == torch.float64 else 1
     g.cur = cur
-    g.buf[0] = a.data_ptr()
-    g.buf[1] = b.data_ptr()
+    es = a.element_size()
+    g.buf[0] = a.data_ptr() + lead * es
+    g.buf[1] = b.data_ptr() + lead * es
     return g
 
 
-def make_coeffs(kind: str, consts=None, arrays=None) -> StencilCoeffs:
+def make_coeffs(kind: str, consts=None, arrays=None, lead: int = 0) -> StencilCoeffs:
+    """Weights: constants, or CUDA tensors laid out like the grid (rows from
+    column `lead`, as in make_grid)."""
     c = StencilCoeffs()
     c.kind = KIND[kind]
     if consts is not None:
@@ -311,5 +324,5 @@ def make_coeffs(kind: str, consts=None, arrays=None) -> StencilCoeffs:
         if len(arrays) != _NARR[kind]:
             raise ValueError("%s needs %d coefficient arrays" % (kind, _NARR[kind]))
         for i, t in enumerate(arrays):
-            c.arr[i] = t.data_ptr()
+            c.arr[i] = t.data_ptr() + lead * t.element_size()
     return c

@@ -15,17 +15,26 @@ namespace mwd {
 template <int K, int BX, int BY>
 constexpr int naive_min_waves() { return (BX * BY >= 1024 && K != K25V) ? 8 : 1; }
 
+// Rows of (x, y) columns per thread: two for the FP32 radius-4 constant
+// star (half the barriers and halo cells per update; its rings still fit 64
+// registers with two planes of prefetch), one elsewhere (the FP64 rings
+// would spill; the radius-1 sweeps gain nothing from it).
+template <int K, typename T>
+constexpr int naive_rows() { return (K == K25C && sizeof(T) == 4) ? 2 : 1; }
+
 template <int K, typename T, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY, (naive_min_waves<K, BX, BY>()))
 naive_sweep_kernel(const T* __restrict__ src, T* __restrict__ dst, Weights<T> w,
                    int nx, int ny, int nz, long long sy, long long sz, int zchunk, int nbx, int nby, int patch)
 {
     constexpr int PF = naive_prefetch<K, T>(false);
-    using G = NaiveGeom<K, BX, BY, PF>;
+    constexpr int RY = naive_rows<K, T>();
+    using G = NaiveGeom<K, BX, BY, PF, false, RY>;
     __shared__ T tile[G::NB][G::TY][G::TX];
     const int t = xcd_tile(blockIdx.x, gridDim.x, patch);
     const int r = t / nbx;
-    naive_block<K, T, BX, BY, PF>(src, dst, w, nx, ny, nz, sy, sz, zchunk, t - r * nbx, r % nby, r / nby, tile);
+    naive_block<K, T, BX, BY, PF, false, RY>(src, dst, w, nx, ny, nz, sy, sz, zchunk, t - r * nbx, r % nby, r / nby,
+                                             tile);
 }
 
 template <int K, typename T>
@@ -42,7 +51,8 @@ static hipError_t launch_naive(const DevGrid& g, const HostWeights& hw, const vo
         w.arr[m] = static_cast<const T*>(hw.org[m]);
     }
     const int zchunk = (R == 1) ? 64 : 128;
-    const long long nbx = (g.nx + BX - 1) / BX, nby = (g.ny + BY - 1) / BY, nbz = (g.nz + zchunk - 1) / zchunk;
+    constexpr int HY = BY * naive_rows<K, T>();  // rows of a block
+    const long long nbx = (g.nx + BX - 1) / BX, nby = (g.ny + HY - 1) / HY, nbz = (g.nz + zchunk - 1) / zchunk;
     const long long nblocks = nbx * nby * nbz;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     // about as many blocks per patch as one XCD (32 CUs) holds at once: two

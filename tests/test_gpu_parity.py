@@ -52,6 +52,19 @@ def test_naive_bitexact(kind, dtype):
     _check(kind, u0, co, 5, *got)
 
 
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_naive_bitexact_z_chunks(kind, dtype):
+    # several z chunks of the naive block (64 planes at radius 1, 128 at
+    # radius 4), each with its steady-state plane loop and a ragged last
+    # chunk; two y blocks even where a block holds several rows per thread
+    n = (70, 75, 300)
+    print("naive z chunks", kind, np.dtype(dtype).name, n, flush=True)
+    u0, co = _inputs(kind, n, dtype)
+    got = run_gpu(kind, u0, co, 3, mode="naive")
+    _check(kind, u0, co, 3, *got)
+
+
 # every compiled (diamond width, x lanes) shape
 MWD_SHAPES = {
     ("7c", "f64"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128)],
@@ -97,6 +110,33 @@ def test_mwd_bitexact_steady_state(case):
     print("mwd steady", case, n, T, flush=True)
     u0, co = _inputs(kind, n, dtype, seed=23)
     got = run_gpu(kind, u0, co, T, mode="mwd", dw=dw, lanes=lanes)
+    _check(kind, u0, co, T, *got)
+
+
+# Rows longer than the padded x extent (sy > nx + 2h), the grid starting at a
+# column `lead` of each row, the rest of every row NaN: nothing outside the
+# padded grid is read (a NaN would reach the results) or written (checked).
+# (kind, dtype, mode, dw, lanes, n, row, lead)
+PADDED_ROW_CASES = [
+    ("7v", np.float64, "mwd", 8, 64, (90, 37, 21), 112, 6),
+    ("7v", np.float64, "mwd", 8, 64, (140, 40, 70), 160, 11),   # steady-state step body
+    ("7v", np.float32, "mwd", 8, 64, (140, 40, 21), 160, 3),
+    ("25c", np.float64, "mwd", 16, 64, (60, 40, 30), 80, 8),
+    ("7c", np.float64, "mwd", 4, 128, (200, 30, 20), 224, 1),
+    ("25c", np.float32, "naive", 0, 0, (70, 75, 140), 96, 5),
+    ("7v", np.float64, "naive", 0, 0, (70, 37, 70), 80, 7),
+]
+
+
+@pytest.mark.parametrize("case", PADDED_ROW_CASES,
+                         ids=lambda c: "%s-%s-%s-dw%d-lx%d-%s-row%d-lead%d" % (
+                             c[0], np.dtype(c[1]).name, c[2], c[3], c[4], "x".join(map(str, c[5])), c[6], c[7]))
+def test_padded_rows(case):
+    kind, dtype, mode, dw, lanes, n, row, lead = case
+    T = 5
+    print("padded rows", case, flush=True)
+    u0, co = _inputs(kind, n, dtype, seed=29)
+    got = run_gpu(kind, u0, co, T, mode=mode, dw=dw, lanes=lanes, row=row, lead=lead)
     _check(kind, u0, co, T, *got)
 
 
