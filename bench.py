@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--energy-sweep", action="store_true",
                     help="energy to solution of the naive sweep and every MWD diamond width on the "
                          "workload's grid, in FP64 and FP32 (GPU socket energy counter)")
+    ap.add_argument("--kind", default=None, choices=["25v"],
+                    help="workload 3 with 13 seeded weight arrays (25-point variable stencil)")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -71,11 +73,29 @@ def make_inputs(w, dtype, windex):
     seed = gridgen.seed_for_config(windex)
     npdt = np.float64 if dtype == "f64" else np.float32
     u0 = gridgen.field(seed, nx, ny, nz, R, *w["field"], dtype=npdt)
+    return u0, workload_coeffs(w, seed, (nx, ny, nz), R, npdt)
+
+
+def workload_coeffs(w, seed, n, R, npdt):
+    """The workload's weights: constants, or the seeded arrays of a variable kind."""
+    import gridgen
     if w["coeffs"] == "7v":
-        co = gridgen.coeffs_7v(seed, nx, ny, nz, R, dtype=npdt)
-    else:
-        co = list(w["coeffs"])
-    return u0, co
+        return gridgen.coeffs_7v(seed, *n, R, dtype=npdt)
+    if w["coeffs"] == "25v":
+        return gridgen.coeffs_25v(seed, *n, R, dtype=npdt)
+    return list(w["coeffs"])
+
+
+def workload(windex, kind=None):
+    """Workload windex; kind "25v" turns workload 3 into its variable-weight
+    form (same grid, field and T; 13 seeded weight arrays)."""
+    import gridgen
+    w = dict(gridgen.workloads()[windex])
+    if kind:
+        if windex != 3 or kind != "25v":
+            raise SystemExit("--kind 25v applies to workload 3 only")
+        w.update(kind="25v", coeffs="25v", name="25v-512^3-T32")
+    return w
 
 
 def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, dw, lanes, halo, meter=None):
@@ -168,10 +188,7 @@ def precision_subrun(S, torch, w, windex, n=(256, 256, 256)):
     R = gridgen.RADIUS[kind]
     seed = gridgen.seed_for_config(windex)
     u64 = gridgen.field(seed, *n, R, *w["field"], dtype=np.float64)
-    if w["coeffs"] == "7v":
-        c64 = gridgen.coeffs_7v(seed, *n, R, dtype=np.float64)
-    else:
-        c64 = list(w["coeffs"])
+    c64 = workload_coeffs(w, seed, n, R, np.float64)
 
     def widened(x):
         return np.asarray(x, dtype=np.float32).astype(np.float64)
@@ -407,7 +424,7 @@ def main():
 
     if a.workload == 5:
         return bench_batch(a, torch, S)
-    w = gridgen.workloads()[a.workload]
+    w = workload(a.workload, a.kind)
     kind = w["kind"]
     dtype = a.dtype or (w["dtype"] if isinstance(w["dtype"], str) else w["dtype"][0])
     nx, ny, nz = w["n"]

@@ -14,6 +14,8 @@ Recipe (the paper's workloads are synthetic grids; there is no dataset):
     order; stream offsets make slab-by-slab generation identical to one pass;
   * 7-point variable weights: c_m ~ U[0.05, 1) for m = 0..6, then per point
     S = ((((((c0+c1)+c2)+c3)+c4)+c5)+c6) and w_m = (0.999 * c_m) / S in FP64;
+    25-point variable weights the same way with m = 0..12 (the 25-point
+    variable workload: workload 3's grid and field with these 13 arrays);
   * FP32 inputs are round-to-nearest casts of the FP64 values.
 """
 from __future__ import annotations
@@ -101,17 +103,17 @@ def field(seed: int, nx: int, ny: int, nz: int, halo: int, lo: float, hi: float,
     return a
 
 
-def coeffs_7v(seed: int, nx: int, ny: int, nz: int, halo: int, dtype=np.float64,
-              total: float = 0.999, outs=None, slab: int = 8) -> list[np.ndarray]:
-    """Seven padded weight arrays C0..C6 of the 7-point variable stencil.
+def coeffs_var(seed: int, nx: int, ny: int, nz: int, halo: int, count: int, dtype=np.float64,
+               total: float = 0.999, outs=None, slab: int = 8) -> list[np.ndarray]:
+    """``count`` padded weight arrays C0..C{count-1} of a variable stencil.
 
     Raw weights come after the field in the same stream (C_m at offset
-    (1 + m) * n_interior); each point's seven weights are scaled to sum to
+    (1 + m) * n_interior); each point's weights are scaled to sum to
     ``total`` (up to rounding) as described in the module docstring.
     """
     n = nx * ny * nz
     plane = nx * ny
-    arrs = outs if outs is not None else [zeros(nx, ny, nz, halo, dtype) for _ in range(7)]
+    arrs = outs if outs is not None else [zeros(nx, ny, nz, halo, dtype) for _ in range(count)]
     for a in arrs:
         a[...] = 0
     views = [interior(a, halo) for a in arrs]
@@ -120,17 +122,30 @@ def coeffs_7v(seed: int, nx: int, ny: int, nz: int, halo: int, dtype=np.float64,
         z0, z1 = zz
         cnt = (z1 - z0) * plane
         raw = []
-        for m in range(7):
+        for m in range(count):
             g = _stream(seed, (1 + m) * n + z0 * plane)
             raw.append((0.05 + 0.95 * g.random(cnt)).reshape(z1 - z0, ny, nx))
         s = raw[0] + raw[1]
-        for m in range(2, 7):
+        for m in range(2, count):
             s = s + raw[m]
-        for m in range(7):
+        for m in range(count):
             views[m][z0:z1] = (total * raw[m]) / s
 
     _parallel(one, _slabs(nz, slab))
     return arrs
+
+
+def coeffs_7v(seed: int, nx: int, ny: int, nz: int, halo: int, dtype=np.float64,
+              total: float = 0.999, outs=None, slab: int = 8) -> list[np.ndarray]:
+    """Seven padded weight arrays C0..C6 of the 7-point variable stencil."""
+    return coeffs_var(seed, nx, ny, nz, halo, 7, dtype, total, outs, slab)
+
+
+def coeffs_25v(seed: int, nx: int, ny: int, nz: int, halo: int, dtype=np.float64,
+               total: float = 0.999, outs=None, slab: int = 8) -> list[np.ndarray]:
+    """Thirteen padded weight arrays C00, C01..C12 of the 25-point variable
+    stencil (Listing 3's order), drawn and scaled like the 7-point ones."""
+    return coeffs_var(seed, nx, ny, nz, halo, 13, dtype, total, outs, slab)
 
 
 def seed_for_config(index: int) -> int:
