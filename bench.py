@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -223,7 +224,8 @@ def precision_subrun(S, torch, w, windex, n=(256, 256, 256)):
         res["vs_" + ref] = {"max_abs_err": err_max,
                             "max_rel_err": err_max / ref_max if ref_max else err_max,
                             "l2_rel_err": err_l2 / ref_l2 if ref_l2 else err_l2,
-                            "a_priori_bound": bound, "within_bound": bool(err_max <= bound)}
+                            "a_priori_bound": bound,
+                            "within_bound": bool(err_max <= bound and math.isfinite(err_l2))}
     return res
 
 

@@ -160,8 +160,9 @@ int stencil_destroy(stencil_plan *plan);
  * on `stream`; on return every grids[i].cur is updated as by stencil_run.
  * The plan must have been created with STENCIL_KIND_MIXED or the grids'
  * common kind.  MWD_TUNE=naive or MWD_TUNE=mwd (environment) forces every
- * grid onto one of the two schedules (a kind without a batched tile shape,
- * or a grid whose plane is 4 GiB or more, stays naive);
+ * grid onto one of the two schedules, MWD_TUNE=mwd:<dw>:<lanes> onto that
+ * batched tile shape (a kind without a batched tile shape, or without that
+ * one, or a grid whose plane is 4 GiB or more, stays naive);
  * MWD_BATCH_GROUP_BYTES (environment, bytes) replaces the 96 MiB budget of
  * one group of naive grids.  Errors: as stencil_run; EINVAL for n outside
  * 1..65535. */

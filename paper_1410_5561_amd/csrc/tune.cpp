@@ -356,6 +356,17 @@ TuneChoice tune_batch_choose(int kind, int dtype, int nx, int ny, int nz, int T)
 {
     const char* e = std::getenv("MWD_TUNE");
     if (e && std::strcmp(e, "naive") == 0) return TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}};
+    const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
+    // MWD_TUNE=mwd:<dw>:<lanes>: that batched tile shape for the kinds that
+    // have it, the naive sweep for the others
+    int fdw = 0, flanes = 0;
+    if (e && std::sscanf(e, "mwd:%d:%d", &fdw, &flanes) == 2) {
+        for (int i = 0; i < nv; ++i)
+            if (kBatchVariantInfo[i].kind == kind && kBatchVariantInfo[i].dw == fdw &&
+                64 * kBatchVariantInfo[i].wpr == flanes)
+                return TuneChoice{STENCIL_MODE_MWD, MwdShape{fdw, kBatchVariantInfo[i].wpr}};
+        return TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}};
+    }
     const bool mwd_only = e && std::strncmp(e, "mwd", 3) == 0;
     // bucket the extents so that a batch of many uneven grids tunes a few
     // representative sizes
@@ -364,7 +375,6 @@ TuneChoice tune_batch_choose(int kind, int dtype, int nx, int ny, int nz, int T)
     if (tune_generic(kind, dtype, bucket(nx), bucket(ny), bucket(nz), T, mwd_only ? 2 : 1, &c) == STENCIL_OK)
         return c;
     // the first compiled variant of this kind
-    const int nv = dtype == 0 ? kNumBatchVariantsF64 : kNumBatchVariants;
     for (int i = 0; i < nv; ++i)
         if (kBatchVariantInfo[i].kind == kind)
             return TuneChoice{STENCIL_MODE_MWD, MwdShape{kBatchVariantInfo[i].dw, kBatchVariantInfo[i].wpr}};

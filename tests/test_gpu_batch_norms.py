@@ -63,6 +63,42 @@ def test_batched_mixed_grids_bitexact_and_replay(dts, T, sched, monkeypatch):
     plan.close()
 
 
+# every shape compiled into the batched tile kernel: (dtype, dw, lanes)
+BATCH_SHAPES = [("f32", 8, 128), ("f32", 4, 256), ("f32", 16, 64),
+                ("f64", 8, 128), ("f64", 4, 256)]
+
+
+@pytest.mark.parametrize("shape", BATCH_SHAPES, ids=lambda c: "%s-dw%d-lx%d" % c)
+def test_batched_each_tile_shape(shape, monkeypatch):
+    """Each batched tile shape pinned explicitly (MWD_TUNE=mwd:<dw>:<lanes>):
+    the grids of a kind with that shape run it, the others the batched naive
+    sweep; every grid bit-exact against the oracle after two replays."""
+    import torch
+    dts, dw, lanes = shape
+    monkeypatch.setenv("MWD_TUNE", "mwd:%d:%d" % (dw, lanes))
+    dtype = np.float64 if dts == "f64" else np.float32
+    print("batched shape", shape, flush=True)
+    specs = [s for s in SPECS if dts == "f32" or s[0] != "7v"]
+    inputs = [_inputs(k, n, dtype, 300 + i) for i, (k, n) in enumerate(specs)]
+    grids, keep, coeffs = [], [], []
+    for (kind, n), (u0, co) in zip(specs, inputs):
+        g, bufs = device_grid(u0, gridgen.RADIUS[kind], 0)
+        c, _ = device_coeffs(kind, co, dtype)
+        grids.append(g)
+        keep.append(bufs)
+        coeffs.append(c)
+    plan = S.Plan("mixed", dts)
+    T = 9
+    for rep in (1, 2):
+        plan.run_batched(grids, coeffs, T)
+        torch.cuda.synchronize()
+        for i, ((kind, n), (u0, co)) in enumerate(zip(specs, inputs)):
+            got = keep[i][grids[i].cur].cpu().numpy()
+            uT, _ = oracle.run(kind, u0, co, rep * T)
+            assert np.array_equal(got, uT), "grid %d (%s %s) after %d runs" % (i, kind, n, rep)
+    plan.close()
+
+
 @pytest.mark.parametrize("dts", ["f64", "f32"])
 def test_norms_against_oracle(dts):
     import torch
