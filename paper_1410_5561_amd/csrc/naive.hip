@@ -37,6 +37,9 @@ naive_sweep_kernel(const T* __restrict__ src, T* __restrict__ dst, Weights<T> w,
                                              tile);
 }
 
+// two 1024-thread (or four 512-thread) workgroups on each of 256 CUs
+constexpr long long kNaiveMinBlocks = 512;
+
 template <int K, typename T>
 static hipError_t launch_naive(const DevGrid& g, const HostWeights& hw, const void* src, void* dst,
                                hipStream_t stream)
@@ -50,9 +53,14 @@ static hipError_t launch_naive(const DevGrid& g, const HostWeights& hw, const vo
         w.c[m] = static_cast<T>(hw.c[m]);
         w.arr[m] = static_cast<const T*>(hw.org[m]);
     }
-    const int zchunk = (R == 1) ? 64 : 128;
     constexpr int HY = BY * naive_rows<K, T>();  // rows of a block
-    const long long nbx = (g.nx + BX - 1) / BX, nby = (g.ny + HY - 1) / HY, nbz = (g.nz + zchunk - 1) / zchunk;
+    const long long nbx = (g.nx + BX - 1) / BX, nby = (g.ny + HY - 1) / HY;
+    // planes per block: 64 (128 at radius 4), halved down to 2 while the
+    // launch has fewer than two workgroups per CU (small grids: more, shorter
+    // z chunks; a block re-reads 2R planes per chunk, from cache at this size)
+    int zchunk = (R == 1) ? 64 : 128;
+    while (zchunk > 2 && nbx * nby * ((g.nz + zchunk - 1) / zchunk) < kNaiveMinBlocks) zchunk /= 2;
+    const long long nbz = (g.nz + zchunk - 1) / zchunk;
     const long long nblocks = nbx * nby * nbz;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     // about as many blocks per patch as one XCD (32 CUs) holds at once: two

@@ -45,7 +45,7 @@ KINDS = ["7c", "7v", "25c", "25v"]
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_naive_bitexact(kind, dtype):
-    n = (70, 37, 21)   # two x blocks, ragged y and z
+    n = (70, 37, 21)   # two x blocks, ragged y and z; z chunks of 2 planes
     print("naive", kind, np.dtype(dtype).name, n, flush=True)
     u0, co = _inputs(kind, n, dtype)
     got = run_gpu(kind, u0, co, 5, mode="naive")
@@ -55,9 +55,10 @@ def test_naive_bitexact(kind, dtype):
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_naive_bitexact_z_chunks(kind, dtype):
-    # several z chunks of the naive block (64 planes at radius 1, 128 at
-    # radius 4), each with its steady-state plane loop and a ragged last
-    # chunk; two y blocks even where a block holds several rows per thread
+    # several z chunks of the naive block (the launch halves its 64 or 128
+    # planes per block until it has two workgroups per CU: 8 or 16 here),
+    # each with its steady-state plane loop, and a ragged last chunk; two y
+    # blocks even where a block holds several rows per thread
     n = (70, 75, 300)
     print("naive z chunks", kind, np.dtype(dtype).name, n, flush=True)
     u0, co = _inputs(kind, n, dtype)
