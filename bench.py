@@ -117,8 +117,6 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
     for _ in range(warmup):
         plan.run(g, c, T)
     torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read()  # drop anything recorded so far
     stream = torch.cuda.current_stream()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
@@ -131,7 +129,15 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
     wall = time.perf_counter() - t0
     ev = evs[0].elapsed_time(evs[-1]) / 1e3
     per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    # kernel durations: as many runs again, with the plan's per-launch events
+    # (launched one by one, not from the captured graph the timed runs replay)
+    plan.profile(True)
+    plan.profile_read()  # drop anything recorded so far
+    for i in range(steps):
+        plan.run(g, c, T)
+    torch.cuda.synchronize()
     prof = plan.profile_read()
+    plan.profile(False)
     desc = plan.describe()
     desc["step_ms"] = {"min": round(per_step[0], 4), "median": round(per_step[len(per_step) // 2], 4),
                        "max": round(per_step[-1], 4)}

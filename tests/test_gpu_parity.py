@@ -114,6 +114,41 @@ def test_mwd_bitexact_steady_state(case):
     _check(kind, u0, co, T, *got)
 
 
+@pytest.mark.parametrize("case", [("7c", np.float64, "naive", 0, 0, 5), ("7c", np.float64, "naive", 0, 0, 4),
+                                  ("7v", np.float32, "mwd", 8, 64, 5), ("25c", np.float64, "mwd", 16, 64, 6),
+                                  ("25c", np.float32, "naive", 0, 0, 3)],
+                         ids=lambda c: "%s-%s-%s-dw%d-T%d" % (c[0], np.dtype(c[1]).name, c[2], c[3], c[5]))
+def test_repeated_runs(case):
+    """One plan run four times in a row on the same grid, with other device
+    work between the calls: after call k the grid holds u_{kT} and
+    u_{kT-1}, bit-exact (cur flips with odd T; MWD scratch is reused)."""
+    import torch
+    import paper_1410_5561_amd as S
+    from gpu_util import device_grid, device_coeffs
+    kind, dtype, mode, dw, lanes, T = case
+    n = (70, 45, 40)
+    R = gridgen.RADIUS[kind]
+    print("repeated runs", case, flush=True)
+    u0, co = _inputs(kind, n, dtype, seed=41)
+    g, keep = device_grid(u0, R, 0)
+    c, ckeep = device_coeffs(kind, co, dtype)
+    plan = S.Plan(kind, "f64" if dtype == np.float64 else "f32", *n, mode=mode, dw=dw, lanes=lanes)
+    other = torch.rand(1 << 20, device="cuda")
+    try:
+        for k in range(1, 5):
+            plan.run(g, c, T)
+            other.mul_(0.5).add_(1.0)          # other work on the stream between the calls
+            S.stencil_norms(g, 0)              # a synchronising library call
+            torch.cuda.synchronize()
+            got = keep[g.cur].cpu().numpy()
+            gotm1 = keep[g.cur ^ 1].cpu().numpy()
+            uT, uTm1 = oracle.run(kind, u0, co, k * T)
+            assert np.array_equal(got, uT), "call %d" % k
+            assert np.array_equal(gotm1, uTm1), "call %d u_{T-1}" % k
+    finally:
+        plan.close()
+
+
 # Rows longer than the padded x extent (sy > nx + 2h), the grid starting at a
 # column `lead` of each row, the rest of every row NaN: nothing outside the
 # padded grid is read (a NaN would reach the results) or written (checked).
