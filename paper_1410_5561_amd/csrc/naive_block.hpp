@@ -31,13 +31,13 @@ namespace mwd {
 // not fit the registers (the 13 coefficient arrays of the 25-point variable
 // stencil); one in the register-capped batched kernel (measured fastest there).
 // (In the standalone sweep every kind fits two 1024-thread blocks per CU,
-// except the 25-point variable stencil: the radius-4 FP64 stencil therefore
-// takes one plane, and the FP32 one, whose threads hold two rows, two.)
+// except the 25-point variable stencil: the radius-4 constant stencil
+// therefore takes two planes, in FP64 for its wider registers and in FP32
+// because its threads hold two rows.)
 template <int K, typename T>
 constexpr int naive_prefetch(bool capped)
 {
     if constexpr (K == K25V) return (capped || sizeof(T) == 8) ? 0 : 1;
-    if constexpr (K == K25C && sizeof(T) == 8) return 1;
     if constexpr (K == K25C) return capped ? 1 : 2;
     return capped ? 1 : 3;
 }
