@@ -57,6 +57,9 @@ def parse():
                          "workload's grid, in FP64 and FP32 (GPU socket energy counter)")
     ap.add_argument("--kind", default=None, choices=["25v"],
                     help="workload 3 with 13 seeded weight arrays (25-point variable stencil)")
+    ap.add_argument("--no-kernel-timing", action="store_true",
+                    help="skip the runs with per-launch events (no roofline): for counter runs, "
+                         "which then see exactly the timed runs")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -99,6 +102,9 @@ def workload(windex, kind=None):
     return w
 
 
+KERNEL_TIMING = True
+
+
 def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, dw, lanes, halo, meter=None):
     """Run warmup + timed steps; return (seconds, plan description, profile).
     With an energy meter, also the energy of repeated runs (outside the timed
@@ -130,14 +136,16 @@ def time_mode(S, torch, kind, dtype, n, u0_dev, co_dev, T, steps, warmup, mode, 
     ev = evs[0].elapsed_time(evs[-1]) / 1e3
     per_step = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     # kernel durations: as many runs again, with the plan's per-launch events
-    # (launched one by one, not from the captured graph the timed runs replay)
-    plan.profile(True)
-    plan.profile_read()  # drop anything recorded so far
-    for i in range(steps):
-        plan.run(g, c, T)
-    torch.cuda.synchronize()
-    prof = plan.profile_read()
-    plan.profile(False)
+    # (skipped with --no-kernel-timing: counter runs then see one set of runs)
+    prof = {"main_ms": 0.0, "main_launches": 0, "other_ms": 0.0, "other_launches": 0}
+    if KERNEL_TIMING:
+        plan.profile(True)
+        plan.profile_read()  # drop anything recorded so far
+        for i in range(steps):
+            plan.run(g, c, T)
+        torch.cuda.synchronize()
+        prof = plan.profile_read()
+        plan.profile(False)
     desc = plan.describe()
     desc["step_ms"] = {"min": round(per_step[0], 4), "median": round(per_step[len(per_step) // 2], 4),
                        "max": round(per_step[-1], 4)}
@@ -394,7 +402,7 @@ def other_workload(a, torch, S, windex, dtype):
     mode_name = {0: "auto", 1: "naive", 2: "mwd"}[desc["mode"]]
     bpl = desc["model_bytes_per_lup"]
     launches = max(1, prof["main_launches"])
-    achieved = bpl * lups * steps / launches / (prof["main_ms"] / 1e3 / launches) / 1e9
+    achieved = bpl * lups * steps / launches / (prof["main_ms"] / 1e3 / launches) / 1e9 if prof["main_ms"] else 0.0
     res = {"workload": w["name"], "dtype": dtype, "value": round(value, 3), "unit": "GLUP/s",
            "steps": steps, "ms_per_step": round(sec * 1e3 / steps, 3),
            "schedule": {"mode": mode_name, "dw": desc["dw"], "lanes": desc["lanes"]},
@@ -420,7 +428,9 @@ def other_workload(a, torch, S, windex, dtype):
 
 
 def main():
+    global KERNEL_TIMING
     a = parse()
+    KERNEL_TIMING = not a.no_kernel_timing
     if a.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus %d is not supported "
                                    "(the stencil path has no multi-GPU form)" % a.gpus}))
@@ -462,7 +472,7 @@ def main():
     # LUPs) over the time the tile kernels ran
     alg_bytes_per_launch = model_bpl * lups * a.steps / main_launches
     avg_launch_s = prof["main_ms"] / 1e3 / main_launches
-    achieved = alg_bytes_per_launch / avg_launch_s / 1e9
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     mode_name = {0: "auto", 1: "naive", 2: "mwd"}[desc["mode"]]
     kname = "mwd_row_kernel" if mode_name == "mwd" else "naive_sweep_kernel"
     shape = "%dx%d" % (desc["dw"], desc["lanes"]) if mode_name == "mwd" else "naive"
