@@ -21,7 +21,12 @@ mwd_row_kernel(MwdArgs<T> a, MwdRow row)
 }
 
 // After the last row, copy u_T and u_{T-1} of every point out of the pair
-// that holds them into the caller's buffers (pair 0).
+// that holds them into the caller's buffers (pair 0).  A block takes 4 rows
+// of 64 points over kGatherPlanes consecutive planes: the pair of each level
+// depends on the row only, and each thread has several planes' copies in
+// flight (short blocks of one plane each were dispatch-bound).
+constexpr int kGatherPlanes = 16;
+
 template <typename T, int R, int DW>
 __global__ void __launch_bounds__(256)
 mwd_gather_kernel(MwdArgs<T> a)
@@ -29,17 +34,25 @@ mwd_gather_kernel(MwdArgs<T> a)
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     if (x >= a.nx) return;
     // y and z stride over the launch's blocks (gridDim.y, gridDim.z <= 65535)
-    for (int z = blockIdx.z; z < a.nz; z += gridDim.z) {
-        for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < a.ny; y += gridDim.y * 4) {
-            const long long off = (long long)z * a.sz + (long long)y * a.sy + x;
+    for (int y = blockIdx.y * 4 + (threadIdx.x >> 6); y < a.ny; y += gridDim.y * 4) {
+        int src[2];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int t = a.nsteps - k;
-                if (t < 1) continue;
-                const int p = pair_of_row(row_of<R, DW>(y, t));
-                if (p != 0) {
-                    const int bi = (a.cur + t) & 1;
-                    a.pair[0][bi][off] = a.pair[p][bi][off];
+        for (int k = 0; k < 2; ++k) {
+            const int t = a.nsteps - k;
+            src[k] = t < 1 ? 0 : pair_of_row(row_of<R, DW>(y, t));
+        }
+        if (src[0] == 0 && src[1] == 0) continue;
+        for (int z0 = blockIdx.z * kGatherPlanes; z0 < a.nz; z0 += gridDim.z * kGatherPlanes) {
+            const int z1 = min(a.nz, z0 + kGatherPlanes);
+#pragma unroll 4
+            for (int z = z0; z < z1; ++z) {
+                const long long off = (long long)z * a.sz + (long long)y * a.sy + x;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    if (src[k] != 0) {
+                        const int bi = (a.cur + a.nsteps - k) & 1;
+                        a.pair[0][bi][off] = a.pair[src[k]][bi][off];
+                    }
                 }
             }
         }
@@ -90,7 +103,8 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         hf.r = G::R;
         hf.sy = g.sy;
         hf.sz = g.sz;
-        dim3 hg((g.nx + 2 * G::R + 63) / 64, std::min((g.ny + 2 * G::R + 3) / 4, kMaxGridYZ), 1);
+        dim3 hg((g.nx + 2 * G::R + 63) / 64, std::min((g.ny + 2 * G::R + 3) / 4, kMaxGridYZ),
+                std::min((g.nz + 2 * G::R + kFillPlanes - 1) / kFillPlanes, kMaxGridYZ));
         if (prof) prof->begin(stream);
         hipLaunchKernelGGL((mwd_halo_fill_kernel<T>), hg, dim3(256), 0, stream, hf);
         if (prof) prof->end(stream, 1);
@@ -111,7 +125,8 @@ static hipError_t run_rows(const DevGrid& g, const HostWeights& hw, int nsteps, 
         if (e != hipSuccess) return e;
     }
     if (!whole) return hipSuccess;
-    dim3 gg((g.nx + 63) / 64, std::min((g.ny + 3) / 4, kMaxGridYZ), std::min(g.nz, kMaxGridYZ));
+    dim3 gg((g.nx + 63) / 64, std::min((g.ny + 3) / 4, kMaxGridYZ),
+            std::min((g.nz + kGatherPlanes - 1) / kGatherPlanes, kMaxGridYZ));
     if (prof) prof->begin(stream);
     hipLaunchKernelGGL((mwd_gather_kernel<T, G::R, DW>), gg, dim3(256), 0, stream, a);
     if (prof) prof->end(stream, 1);

@@ -228,16 +228,20 @@ struct HaloFill {
 };
 
 // Lanes take x; rows y stride over the grid's y blocks (the launch may have
-// fewer y blocks than the rows need: gridDim.y is at most 65535).
+// fewer y blocks than the rows need: gridDim.y is at most 65535); planes
+// [z0, z1) of the padded range [-r, nz + r).
 template <typename T>
-__device__ __forceinline__ void halo_fill_one(const HaloFill<T>& e)
+__device__ __forceinline__ void halo_fill_one(const HaloFill<T>& e, int z0, int z1)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63) - e.r;
     if (x >= e.nx + e.r) return;
     for (int y = blockIdx.y * 4 + (threadIdx.x >> 6) - e.r; y < e.ny + e.r; y += gridDim.y * 4) {
         const bool col_inside = x >= 0 && x < e.nx && y >= 0 && y < e.ny;
-        for (int z = -e.r; z < e.nz + e.r; ++z) {
-            if (col_inside && z == 0) z = e.nz;  // skip the interior of an interior column
+        for (int z = z0; z < z1; ++z) {
+            if (col_inside && z >= 0 && z < e.nz) {  // skip the interior of an interior column
+                z = e.nz - 1;
+                continue;
+            }
             const long long off = (long long)z * e.sz + (long long)y * e.sy + x;
             const T v = e.src[off];
 #pragma unroll
@@ -248,18 +252,25 @@ __device__ __forceinline__ void halo_fill_one(const HaloFill<T>& e)
 
 // Largest y or z extent of a launch grid.
 constexpr int kMaxGridYZ = 65535;
+// Planes per block of the single-grid fill: the columns on the domain's x
+// and y faces hold boundary values in every plane, and one thread walking
+// all of them in sequence was latency-bound.
+constexpr int kFillPlanes = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(256) mwd_halo_fill_kernel(HaloFill<T> e)
 {
-    halo_fill_one(e);
+    // z chunks stride over the launch's blocks (gridDim.z <= 65535)
+    for (int z0 = -e.r + (int)blockIdx.z * kFillPlanes; z0 < e.nz + e.r; z0 += gridDim.z * kFillPlanes)
+        halo_fill_one(e, z0, min(e.nz + e.r, z0 + kFillPlanes));
 }
 
-// Batched: entry blockIdx.z of a device table.
+// Batched: entry blockIdx.z of a device table, all planes.
 template <typename T>
 __global__ void __launch_bounds__(256) mwd_halo_fill_table_kernel(const HaloFill<T>* __restrict__ table)
 {
-    halo_fill_one(table[blockIdx.z]);
+    const HaloFill<T>& e = table[blockIdx.z];
+    halo_fill_one(e, -e.r, e.nz + e.r);
 }
 
 // The tile (diamond b of the row, x tile j) computed by one workgroup.
