@@ -172,3 +172,28 @@ def test_model_cache_block_golden(L):
         assert S.stencil_model_cache_block(kind, "f32", c["Dw"], 32, c["N_F"]) == 128 * c["C_S_per_Nxb"]
     assert L.stencil_model_cache_block(9, 0, 8, 64, 1) < 0
     assert L.stencil_model_cache_block(0, 0, 8, 0, 1) < 0
+
+
+def test_make_grid_describes_padded_rows():
+    """The binding's grid description (no device needed: CPU tensors stand in
+    for device buffers): strides from the tensors, the first buffer element at
+    column `lead`, nx given or taken from the row length; rows too short for
+    the grid are refused."""
+    import torch
+    h, nx, ny, nz, W, lead = 1, 20, 6, 5, 32, 7
+    a = torch.zeros((nz + 2 * h, ny + 2 * h, W), dtype=torch.float64)
+    b = torch.zeros_like(a)
+    g = S.make_grid(a, b, h, 1, nx=nx, lead=lead)
+    assert (g.nx, g.ny, g.nz, g.halo, g.cur, g.dtype) == (nx, ny, nz, h, 1, 0)
+    assert (g.sy, g.sz) == (W, W * (ny + 2 * h))
+    assert g.buf[0] == a.data_ptr() + lead * 8 and g.buf[1] == b.data_ptr() + lead * 8
+    g2 = S.make_grid(a, b, h)                      # rows without padding
+    assert (g2.nx, g2.buf[0]) == (W - 2 * h, a.data_ptr())
+    with pytest.raises(ValueError):
+        S.make_grid(a, b, h, nx=nx, lead=W - nx - 2 * h + 1)
+    c = S.make_coeffs("7v", arrays=[a] * 7, lead=lead)
+    assert c.arr[3] == a.data_ptr() + lead * 8
+
+
+def test_binding_checks_the_library_abi_version(L):
+    assert L.stencil_abi_version() == S.ABI_VERSION
