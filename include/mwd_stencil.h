@@ -111,7 +111,7 @@ typedef struct {
  * (STENCIL_KIND_MIXED with nx = ny = nz = 0 for batched plans).  p == NULL
  * asks for the autotuned schedule (Sec. II-A: parameters are auto-tuned);
  * tuning runs at the first stencil_run (synchronously, on a proxy grid of
- * the same x-y extent, at most 32 GiB of arrays, that it allocates and
+ * the same x-y extent, at most 8 GiB of arrays, that it allocates and
  * frees), predicting the whole run for that call's T; the choice is kept
  * for the plan's later runs.  Errors: EINVAL (bad kind/dtype/size/params),
  * EUNSUPPORTED (parameters no kernel implements), ENOMEM. */

@@ -55,7 +55,7 @@ bool g_file_loaded = false;
 
 // The proxy grid holds at most this many bytes (its arrays: two levels, four
 // scratch arrays, the coefficient arrays) and at least this many planes.
-constexpr size_t kProxyBytes = size_t(32) << 30;
+constexpr size_t kProxyBytes = size_t(8) << 30;
 constexpr int kMinProxyNz = 64;
 // A tile kernel that spills more than this to scratch memory (bytes per lane)
 // is not tried; a few spilled registers outside the step loop cost little.
