@@ -268,3 +268,52 @@ def test_extents_beyond_the_launch_grid_limit(case):
     _check(kind, u0, co, T, *got)
     got = run_gpu(kind, u0, co, T, mode="naive")
     _check(kind, u0, co, T, *got)
+
+
+def _random_cases(count=24, seed=1410):
+    """Seeded random draws over the whole parameter space: kind, dtype,
+    schedule (naive or any compiled MWD shape), extents (1..150 in x, 1..90
+    in y, 1..80 in z), T (0..15), halo (R or R + 1..3), starting buffer, and
+    rows padded beyond the grid.  Sizes stay small enough for the oracle."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        kind = KINDS[rng.integers(len(KINDS))]
+        dts = ("f64", "f32")[rng.integers(2)]
+        shapes = [(0, 0)] + MWD_SHAPES[(kind, dts)]
+        dw, lanes = shapes[rng.integers(len(shapes))]
+        n = (int(rng.integers(1, 151)), int(rng.integers(1, 91)), int(rng.integers(1, 81)))
+        if lanes == 256:
+            n = (int(rng.integers(200, 600)),) + n[1:]
+        T = int(rng.integers(0, 16))
+        R = gridgen.RADIUS[kind]
+        halo = R + (int(rng.integers(1, 4)) if rng.random() < 0.3 else 0)
+        cur = int(rng.integers(2))
+        pad = int(rng.integers(0, 20)) if rng.random() < 0.3 else 0
+        out.append((i, kind, dts, dw, lanes, n, T, halo, cur, pad))
+    return out
+
+
+@pytest.mark.parametrize("case", _random_cases(), ids=lambda c: "r%d-%s-%s-dw%d-lx%d-%s-T%d-h%d-c%d-p%d" % (
+    c[0], c[1], c[2], c[3], c[4], "x".join(map(str, c[5])), c[6], c[7], c[8], c[9]))
+def test_random_cases(case):
+    i, kind, dts, dw, lanes, n, T, halo, cur, pad = case
+    dtype = np.float64 if dts == "f64" else np.float32
+    print("random case", case, flush=True)
+    R = gridgen.RADIUS[kind]
+    u0 = gridgen.field(500 + i, *n, halo, -1.0, 1.0, dtype)
+    if kind == "7c":
+        co = gridgen.C7
+    elif kind == "25c":
+        co = gridgen.C25
+    elif kind == "7v":
+        co = [c.astype(dtype) for c in gridgen.coeffs_7v(500 + i, *n, halo)]
+    else:
+        co = [c.astype(dtype) for c in gridgen.coeffs_25v(500 + i, *n, halo)]
+    mode = "naive" if dw == 0 else "mwd"
+    row = u0.shape[2] + pad if pad else None
+    got = run_gpu(kind, u0, co, T, mode=mode, dw=dw, lanes=lanes, halo=halo, cur=cur, row=row, lead=pad // 2)
+    uT, uTm1 = oracle.run(kind, u0, co, T, halo=halo)
+    assert np.array_equal(got[0], uT), "u_T differs"
+    if T > 0:
+        assert np.array_equal(got[1], uTm1), "u_{T-1} differs"
