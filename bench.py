@@ -537,7 +537,7 @@ def main():
         out["energy"] = en
         meter.close()
     if a.sweep:
-        shapes = {1: [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
+        shapes = {1: [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (10, 64), (16, 64)],
                   4: [(8, 64), (8, 128), (16, 64)]}[R]
         sw = []
         for dw, lx in shapes:

@@ -78,7 +78,7 @@ def table() -> list[str]:
     ]
     for kind in ("7c", "7v", "25c", "25v"):
         for dtype, elem in (("f64", 8), ("f32", 4)):
-            for dw in (4, 8, 16):
+            for dw in (4, 8, 10, 16):
                 for lanes in (64, 128, 256):
                     try:
                         r = S.stencil_kernel_resources(kind, dtype, dw, lanes)

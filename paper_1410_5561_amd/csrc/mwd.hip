@@ -37,7 +37,7 @@ bool mwd_supported(int kind, int dtype, const MwdShape& s) { return find_entry(k
 int mwd_shapes(int kind, int dtype, MwdShape* out, int cap)
 {
     if (kind < 0 || kind > 3 || dtype < 0 || dtype > 1) return 0;
-    static const int dws[] = {4, 8, 16};
+    static const int dws[] = {4, 8, 10, 16};
     static const int wprs[] = {1, 2, 4};
     int n = 0;
     for (int dw : dws)

@@ -686,9 +686,9 @@ __device__ __forceinline__ void mwd_tile(const MwdArgs<T>& a, const MwdRow& row,
         generic_chunks(ti, s_fast_end, s_last + 1);
     };
     // the wave's row type, if its level sets are those of an unclipped tile;
-    // shapes with more than four types (Dw 16 at radius 1, whose 15 levels
+    // shapes with more than five types (Dw 16 at radius 1, whose 15 levels
     // do not fit the registers anyway) compile the untyped sweep only
-    constexpr int NTYPES = CR::ntypes() <= 4 ? CR::ntypes() : 0;
+    constexpr int NTYPES = CR::ntypes() <= 5 ? CR::ntypes() : 0;
     int rtype = -1;
     static_for<0, NTYPES>([&](auto ic) MWD_INLINE {
         constexpr int yt = CR::rep(decltype(ic)::value);

@@ -71,7 +71,7 @@ MWD_SHAPES = {
     ("7c", "f64"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128)],
     ("7c", "f32"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
     ("7v", "f64"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128)],
-    ("7v", "f32"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (16, 64)],
+    ("7v", "f32"): [(4, 64), (4, 128), (4, 256), (8, 64), (8, 128), (10, 64), (16, 64)],
     ("25c", "f64"): [(8, 64), (8, 128), (16, 64)],
     ("25c", "f32"): [(8, 64), (8, 128), (16, 64)],
     ("25v", "f64"): [(8, 64), (8, 128), (16, 64)],
