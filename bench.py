@@ -347,7 +347,7 @@ def energy_sweep(a, torch, S, windex):
     kind, n, T = w["kind"], w["n"], w["T"]
     R = gridgen.RADIUS[kind]
     shapes = {1: [("naive", 0, 0), ("mwd", 4, 64), ("mwd", 4, 128), ("mwd", 4, 256), ("mwd", 8, 64),
-                  ("mwd", 8, 128)],
+                  ("mwd", 8, 128), ("mwd", 10, 64)],
               4: [("naive", 0, 0), ("mwd", 8, 64), ("mwd", 8, 128), ("mwd", 16, 64)]}[R]
     meter = energy.EnergyMeter()
     out = {"workload": w["name"], "meter": "AMD SMI energy counter of the GPU socket", "points": []}
