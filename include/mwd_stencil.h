@@ -111,9 +111,13 @@ typedef struct {
  * (STENCIL_KIND_MIXED with nx = ny = nz = 0 for batched plans).  p == NULL
  * asks for the autotuned schedule (Sec. II-A: parameters are auto-tuned);
  * tuning runs at the first stencil_run (synchronously, on a proxy grid of
- * the same x-y extent, at most 8 GiB of arrays, that it allocates and
- * frees), predicting the whole run for that call's T; the choice is kept
- * for the plan's later runs.  Errors: EINVAL (bad kind/dtype/size/params),
+ * the same x-y extent that it allocates and frees: as many planes as 8 GiB
+ * of arrays hold, but at least 64 and at most nz; if the proxy cannot be
+ * allocated, the plan runs the naive sweep), predicting the whole run for
+ * that call's T; the choice is kept for the plan's later runs.
+ * MWD_TUNE=naive or MWD_TUNE=mwd:<dw>:<lanes> (environment) replaces the
+ * tuning by that choice (a shape no kernel implements is ignored).
+ * Errors: EINVAL (bad kind/dtype/size/params),
  * EUNSUPPORTED (parameters no kernel implements), ENOMEM. */
 int stencil_create(stencil_plan **out, int32_t kind, int32_t dtype,
                    int32_t nx, int32_t ny, int32_t nz, const stencil_params *p);

@@ -267,8 +267,16 @@ int tune_generic(int kind, int dtype, int nx, int ny, int nz, int T, int batch, 
             }
     } else {
         cands.push_back(TuneChoice{STENCIL_MODE_NAIVE, MwdShape{0, 0}});
+        // the proxy's plane (and the run's, at least as large) must be one the
+        // MWD kernel can address; otherwise MWD is not timed at all
+        const int h = radius_of(kind);
+        const long long proxy_sz = (long long)(nx + 2 * h) * (long long)(ny + 2 * h);
         MwdShape shapes[16];
-        const int ns = mwd_shapes(kind, dtype, shapes, 16);
+        const bool plane_ok = mwd_plane_ok(proxy_sz, dtype);
+        const int ns = plane_ok ? mwd_shapes(kind, dtype, shapes, 16) : 0;
+        if (!plane_ok && tune_verbose())
+            std::fprintf(stderr, "[mwd tune] kind %d dtype %d %dx%d: plane of 4 GiB or more, naive only\n", kind,
+                         dtype, nx, ny);
         for (int i = 0; i < ns; ++i) {
             size_t scratch = 0;
             const bool spill_ok =

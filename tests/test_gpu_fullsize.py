@@ -110,3 +110,54 @@ def test_f32_error_subrun_against_f64_oracle():
     rl2, rmx = onorms.residual_norms(r32, r32m1, 1)
     assert abs(l2 - rl2) <= 1e-12 * rl2 and mx == rmx
     plan.close()
+
+
+def test_autotuned_plan_on_a_plane_of_4gib_runs_naive():
+    """A padded plane of 4 GiB or more (FP32, 32769^2 elements) is beyond the
+    MWD tile kernel's 32-bit plane offsets: the autotuner does not time MWD
+    on it and the plan runs the naive sweep, whose 64-bit addressing is
+    checked bit for bit on whole x rows and y columns (one step: each
+    output needs only its neighbours, so the oracle runs on three rows or
+    columns of the input with their true neighbours as the fixed boundary).
+    About 26 GB of device memory."""
+    import torch
+    nx = ny = 32767
+    nz, R, T = 1, 1, 1
+    nxp = nx + 2 * R
+    assert nxp * nxp * 4 >= (1 << 32)
+    print("plane of 4 GiB: 7c f32 %dx%dx%d, allocating" % (nx, ny, nz), flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1410)
+    a = torch.empty((nz + 2 * R, nxp, nxp), dtype=torch.float32, device="cuda")
+    a.uniform_(-1.0, 1.0, generator=gen)
+    b = a.clone()
+    g = S.make_grid(a, b, R, 0)
+    coeffs = S.make_coeffs("7c", consts=list(gridgen.C7))
+    plan = S.Plan("7c", "f32", nx, ny, nz)   # autotuned
+    print("plane of 4 GiB: running", flush=True)
+    plan.run(g, coeffs, T)
+    torch.cuda.synchronize()
+    desc = plan.describe()
+    print("plane of 4 GiB: schedule", desc, flush=True)
+    assert desc["mode"] == S.MODE["naive"]
+    assert g.cur == 1
+    rng = np.random.default_rng(1410)
+    ys = [0, 1, ny // 2, ny - 1, int(rng.integers(ny))]
+    xs = [0, nx // 2 - 1, nx - 1, int(rng.integers(nx))]
+    checked = 0
+    for y in ys:   # interior row y: input rows y - 1 .. y + 1 of every plane
+        sub = np.ascontiguousarray(a[:, y:y + 3, :].cpu().numpy())
+        ref, _ = oracle.run("7c", sub, gridgen.C7, T, halo=R)
+        got = b[R:R + nz, y + R:y + R + 1, R:R + nx].cpu().numpy()
+        assert np.array_equal(got, ref[R:R + nz, R:R + 1, R:R + nx]), "row y=%d differs" % y
+        checked += got.size
+    for x in xs:   # interior column x
+        sub = np.ascontiguousarray(a[:, :, x:x + 3].cpu().numpy())
+        ref, _ = oracle.run("7c", sub, gridgen.C7, T, halo=R)
+        got = b[R:R + nz, R:R + ny, x + R:x + R + 1].cpu().numpy()
+        assert np.array_equal(got, ref[R:R + nz, R:R + ny, R:R + 1]), "column x=%d differs" % x
+        checked += got.size
+    print("plane of 4 GiB: %d points bit-exact" % checked, flush=True)
+    plan.close()
+    del a, b, g
+    torch.cuda.empty_cache()
