@@ -113,3 +113,61 @@ def test_batched_run_on_a_side_stream():
             uT, _ = oracle.run(kind, u0, co, T)
             assert np.array_equal(got[i].cpu().numpy(), uT), "grid %d (%s %s), call %d" % (i, kind, n, call)
     plan.close()
+
+
+def test_two_plans_in_flight_on_two_streams():
+    """Distinct plans run concurrently on distinct streams: an MWD 7v run and
+    an MWD 25c run enqueued on two side streams without synchronizing in
+    between, each bit-exact."""
+    import torch
+    cases = [("7v", (90, 41, 30), 9, 8, 64), ("25c", (60, 48, 36), 5, 16, 64)]
+    print("two streams", cases, flush=True)
+    work = []
+    for i, (kind, n, T, dw, lanes) in enumerate(cases):
+        u0, co = _inputs(kind, n, seed=80 + i)
+        st = _Staged(kind, u0, co)
+        plan = S.Plan(kind, "f64", *n, mode="mwd", dw=dw, lanes=lanes)
+        work.append((kind, n, T, u0, co, st, plan, torch.cuda.Stream()))
+    big = torch.ones(1 << 28, device="cuda")
+    torch.cuda.synchronize()
+    for kind, n, T, u0, co, st, plan, s in work:
+        with torch.cuda.stream(s):
+            _busy(big, rounds=8)
+            st.stage()
+            plan.run(st.grid, st.coeffs, T, stream=s)
+    torch.cuda.synchronize()
+    for kind, n, T, u0, co, st, plan, s in work:
+        uT, uTm1 = oracle.run(kind, u0, co, T)
+        assert np.array_equal((st.a, st.b)[st.grid.cur].cpu().numpy(), uT), kind
+        assert np.array_equal((st.a, st.b)[st.grid.cur ^ 1].cpu().numpy(), uTm1), kind
+        plan.close()
+
+
+def test_norms_from_two_host_threads():
+    """stencil_norms called from two host threads at once, each on its own
+    stream and grid (the library's partials buffer is shared per device and
+    held under a lock): every result equals the oracle's."""
+    import threading
+    import torch
+    grids = []
+    for i, n in enumerate([(70, 37, 21), (33, 64, 40)]):
+        u0, co = _inputs("7c", n, seed=90 + i)
+        st = _Staged("7c", u0, co)
+        st.stage()
+        grids.append((st, onorms.grid_norms(u0, 1)))
+    torch.cuda.synchronize()
+    errors = []
+
+    def worker(st, ref):
+        s = torch.cuda.Stream()
+        for _ in range(50):
+            l2, mx = S.stencil_norms(st.grid, 0, stream=s)
+            if not (abs(l2 - ref[0]) <= 1e-13 * ref[0] and mx == ref[1]):
+                errors.append((l2, mx, ref))
+
+    threads = [threading.Thread(target=worker, args=g) for g in grids]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors[:3]
