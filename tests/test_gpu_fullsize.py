@@ -21,17 +21,24 @@ from oracle import norms as onorms
 pytestmark = pytest.mark.gpu
 
 
-def _run_full(windex, dtype):
+def _run_full(windex, dtype, kind=None):
+    """Workload windex at full size with the autotuned plan; kind "25v" turns
+    workload 3 into its variable-weight form (13 seeded weight arrays), as
+    the benchmark's --kind 25v does."""
     import torch
-    w = gridgen.workloads()[windex]
+    w = dict(gridgen.workloads()[windex])
+    if kind == "25v":
+        assert windex == 3
+        w.update(kind="25v", coeffs="25v", name="25v-512^3-T32")
     kind, (nx, ny, nz), T = w["kind"], w["n"], w["T"]
     R = gridgen.RADIUS[kind]
     seed = gridgen.seed_for_config(windex)
     npdt = np.float64 if dtype == "f64" else np.float32
     print("workload", windex, w["name"], dtype, "generating", flush=True)
     u0 = gridgen.field(seed, nx, ny, nz, R, *w["field"], dtype=npdt)
-    if w["coeffs"] == "7v":
-        co = gridgen.coeffs_7v(seed, nx, ny, nz, R, dtype=npdt)
+    if w["coeffs"] in ("7v", "25v"):
+        gen = gridgen.coeffs_7v if w["coeffs"] == "7v" else gridgen.coeffs_25v
+        co = gen(seed, nx, ny, nz, R, dtype=npdt)
         c_dev = [torch.from_numpy(c).cuda() for c in co]
         coeffs = S.make_coeffs(kind, arrays=c_dev)
     else:
@@ -78,6 +85,19 @@ def test_fullsize_sampled_bitexact(windex, dtype, count):
     u0max = float(np.max(np.abs(u0)))
     assert np.isfinite(l2) and mx <= u0max   # weights are non-negative with sum < 1
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fullsize_25v_sampled_bitexact(dtype):
+    """The variable-weight 25-point form of workload 3 (512^3, T = 32, 13
+    weight arrays) at full size with the autotuned plan, as the benchmark's
+    --kind 25v line runs it: sampled points, whole x rows and y columns."""
+    import torch
+    w, u0, co, g, bufs, plan, keep = _run_full(3, dtype, kind="25v")
+    _check_samples(w, u0, co, g, bufs, 5)
+    plan.close()
+    del bufs, keep, g
+    torch.cuda.empty_cache()
 
 
 def test_f32_error_subrun_against_f64_oracle():
